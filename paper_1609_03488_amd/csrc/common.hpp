@@ -1,0 +1,168 @@
+// Shared host/device definitions of the solver engine.
+//
+// An *engine* advances a set of problem instances together.  Every instance
+// owns one contiguous region of device memory:
+//
+//   [ scalars: NSC doubles | counters: NCNT ints | X vectors (NXV x nxs) | Y vectors (NYV x nys) ]
+//
+// X vectors have the length n of the variable, Y vectors the length m of the
+// constraint rows; nxs / nys are those lengths rounded up to XY_ALIGN elements.
+// Kernels walk *tile tables*: every tile lies inside one instance, so a single
+// launch covers all instances, and the per-instance arithmetic (including the
+// fixed-order reductions) does not depend on which other instances are in it.
+#pragma once
+#include <cstdint>
+
+namespace cgs {
+
+// ---------------------------------------------------------------- vectors
+// X-space vectors (length n)
+enum XVec : int {
+    XU = 0,   // u_x
+    XG,       // g_x  (embedding vector, x part)
+    XC,       // c
+    XZ,       // CG iterate: z_x = (I + A^T A)^{-1} (u_x - A^T w_y); warm start
+    XR,       // CG residual
+    XP,       // CG direction
+    XQ,       // (I + A^T A) p
+    XH,       // CG right-hand side
+    XT,       // scratch (A^T y for residuals / diagnostics)
+    NXV
+};
+// Y-space vectors (length m)
+enum YVec : int {
+    YU = 0,   // u_y
+    YV,       // v_s (the y-block of v)
+    YG,       // g_y
+    YB,       // b
+    YW,       // w_y = u_y + v_s
+    YZ,       // z_y = w_y + A z_x
+    YT,       // scratch (A p, A u_x)
+    NYV
+};
+
+// ---------------------------------------------------------------- scalars
+// per-instance FP64 scalars
+enum Scal : int {
+    SC_TAU = 0, SC_KAPPA, SC_ETA, SC_UT,        // tau, kappa, eta, u~_tau
+    SC_RR, SC_PQ, SC_ALPHA, SC_BETA,           // CG: ||r||^2, <p,q>, alpha, beta
+    SC_CGTOL, SC_HN,                           // CG stop threshold on ||r||, ||rhs||
+    SC_NB, SC_NC,                              // ||b||, ||c||
+    SC_CX, SC_BY,                              // c^T x, b^T y at the last check
+    SC_RP, SC_RD, SC_GAP,                      // residuals at the last check
+    SC_ACTIVE,                                 // 1 while the instance runs
+    SC_PHASE,                                  // 0: setup pending, 1: iterating
+    SC_CGACT,                                  // 1 while CG of the instance runs
+    SC_CGIT,                                   // CG iterations in the current solve
+    SC_CGTOT,                                  // CG iterations since set_data
+    SC_ITER,                                   // ADMM iterations done
+    SC_STATUS,                                 // CGS_* outcome
+    SC_SETUPIT,                                // CG iterations of the setup solve
+    SC_CUX, SC_BUY,                            // raw c^T u_x, b^T u_y at the last check
+    NSC_USED
+};
+constexpr int NSC = 32;      // doubles reserved per instance (256 bytes)
+constexpr int NCNT = 64;     // int counters reserved per instance (256 bytes)
+constexpr int XY_ALIGN = 64; // elements
+constexpr int REGION_HDR = NSC * 8 + NCNT * 4;  // 512 bytes
+
+// ---------------------------------------------------------------- gates
+enum Gate : int {
+    G_ALL = 0,        // every instance
+    G_SETUP = 1,      // active and setup pending
+    G_SETUP_CG = 2,   // ... and CG running
+    G_ADMM = 3,       // active and iterating
+    G_ADMM_CG = 4,    // ... and CG running
+    G_CHECK = 5,      // active and iterating (termination test)
+    G_ANY_CG = 6      // CG running, whatever the phase (diagnostic solves)
+};
+
+// ---------------------------------------------------------------- tables
+struct InstDesc {
+    char* base;          // region base (device address)
+    int64_t n, m;        // variables, constraint rows
+    int64_t nxs, nys;    // padded vector strides (elements)
+    int64_t l;           // nonnegative rows
+    int32_t xt0, xt1;    // X-tile range
+    int32_t yt0, yt1;    // Y-tile range
+    int32_t sg0, sg1;    // SOC segment range
+    int32_t id0, id1;    // identity-block range
+};
+
+// A tile of an X or Y vector: `len` elements from instance-local `start`.
+// seg >= 0: the rows belong to second-order cone `seg` (Y tiles only).
+struct VecTile {
+    int32_t inst;
+    int32_t seg;
+    int64_t start;
+    int32_t len;
+    int32_t pad;
+};
+
+struct SocSeg {
+    int32_t inst;
+    int32_t ntiles;      // Y tiles covering the segment
+    int32_t yt0;         // first of those tiles
+    int32_t pad;
+    int64_t start;       // instance-local row of the cone's first entry (t)
+    int64_t len;
+};
+
+struct IdBlock {         // out[row0+i] += scale * in[col0+i], i < len
+    int64_t row0, col0, len;
+    double scale;
+};
+
+struct ConvBlock {       // full convolution of n_in inputs with k taps
+    int64_t row0, col0, n_in, k, kpad;
+    const void* w_fwd;   // taps reversed (correlation order for A x), kpad entries
+    const void* w_adj;   // taps in order (correlation order for A^T y), kpad entries
+    double scale;
+};
+
+struct ConvTile {        // CONV_TILE outputs starting at block-local `start`
+    int32_t inst;
+    int32_t blk;
+    int64_t start;
+};
+
+struct DenseBlock {      // rows x cols block
+    int64_t row0, col0, rows, cols;
+    int64_t ld, ldt;     // leading dimensions of a (rows x ld) and at (cols x ldt)
+    const void* a;       // working precision, row-major
+    const void* at;      // its transpose, row-major
+    const void* a16;     // BF16 copies (CGS_BF16 only) or null
+    const void* at16;
+    double scale;
+};
+
+struct DenseTile {       // `nr` rows of the (possibly transposed) block from r0
+    int32_t inst;
+    int32_t blk;
+    int64_t r0;
+    int32_t nr;
+    int32_t pad;
+};
+
+struct Tables {
+    const InstDesc* inst;
+    const VecTile* xt;
+    const VecTile* yt;
+    const SocSeg* seg;
+    double* seg_val;     // 2 per segment: head value, tail sum of squares
+    int* seg_cnt;        // 1 per segment
+    const IdBlock* ids;
+    double* xpart;       // 4 per X tile
+    double* ypart;       // 4 per Y tile
+    int nx_tiles, ny_tiles, nseg, ninst;
+};
+
+constexpr int VEC_TILE = 1024;     // elements per X/Y tile
+constexpr int VEC_NT = 256;        // threads per vector-kernel block
+constexpr int CONV_TILE_F32 = 2048;  // outputs per convolution tile (256 threads x 8)
+constexpr int CONV_TILE_F64 = 1024;  // (256 threads x 4)
+constexpr int CONV_R_F32 = 8;        // taps are padded to a multiple of this
+constexpr int CONV_R_F64 = 4;
+constexpr int DENSE_ROWS = 4;        // rows per dense-GEMV tile
+
+}  // namespace cgs

@@ -1,0 +1,497 @@
+// Host orchestration of the solver engine.
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace cgs {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+const char* last_error() { return g_err.c_str(); }
+
+// ---------------------------------------------------------------- validation
+int validate_cone(int64_t m, int64_t l, const int64_t* q, int64_t nq) {
+    if (l < 0 || nq < 0) return fail(CGS_ECONE, "negative cone count (l=%lld, nq=%lld)", (long long)l, (long long)nq);
+    if (nq > 0 && q == nullptr) return fail(CGS_EINVAL, "q is null with nq=%lld", (long long)nq);
+    int64_t tot = l;
+    for (int64_t i = 0; i < nq; ++i) {
+        if (q[i] < 1) return fail(CGS_ECONE, "second-order cone %lld has size %lld < 1", (long long)i, (long long)q[i]);
+        tot += q[i];
+    }
+    if (tot != m)
+        return fail(CGS_ECONE, "cones cover %lld rows but the operator has m=%lld", (long long)tot, (long long)m);
+    return CGS_OK;
+}
+
+int validate_settings(const cgs_settings* s) {
+    if (!s) return fail(CGS_EINVAL, "settings is null");
+    if (!(s->eps > 0.0) || !std::isfinite(s->eps)) return fail(CGS_EINVAL, "eps must be finite and > 0");
+    if (!(s->alpha > 0.0 && s->alpha < 2.0)) return fail(CGS_EINVAL, "alpha must lie in (0, 2)");
+    if (s->max_iters < 1) return fail(CGS_EINVAL, "max_iters must be >= 1");
+    if (s->check_every < 1) return fail(CGS_EINVAL, "check_every must be >= 1");
+    if (s->precision < CGS_FP64 || s->precision > CGS_BF16) return fail(CGS_EINVAL, "unknown precision %d", s->precision);
+    if (s->cg_max_iters < 1 || s->cg_max_iters > 10000) return fail(CGS_EINVAL, "cg_max_iters must be in [1, 10000]");
+    if (!(s->cg_tol >= 0.0) || !(s->cg_rate >= 0.0) || !(s->cg_floor >= 0.0) ||
+        !std::isfinite(s->cg_tol) || !std::isfinite(s->cg_rate) || !std::isfinite(s->cg_floor))
+        return fail(CGS_EINVAL, "cg_tol, cg_rate, cg_floor must be finite and >= 0");
+    if (!(s->setup_tol > 0.0) || !std::isfinite(s->setup_tol)) return fail(CGS_EINVAL, "setup_tol must be finite and > 0");
+    if (s->setup_max_iters < 1) return fail(CGS_EINVAL, "setup_max_iters must be >= 1");
+    if (s->bf16_final_iters < 0) return fail(CGS_EINVAL, "bf16_final_iters must be >= 0");
+    return CGS_OK;
+}
+
+// ---------------------------------------------------------------- layouts
+static int64_t conv_r(int precision) { return precision == CGS_FP64 ? CONV_R_F64 : CONV_R_F32; }
+static int64_t conv_tile(int precision) { return precision == CGS_FP64 ? CONV_TILE_F64 : CONV_TILE_F32; }
+static int64_t dense_ld(int64_t cols) { return round_up(cols, 8); }
+
+int64_t staging_doubles(const cgs_op& op, int64_t max_vec) {
+    int64_t need = std::max<int64_t>(max_vec, int64_t(1) << 16);
+    for (const auto& b : op.blocks) {
+        if (b.kind == CGS_BLOCK_CONV) need = std::max<int64_t>(need, 2 * round_up(b.k, 8));
+        if (b.kind == CGS_BLOCK_DENSE) {
+            need = std::max<int64_t>(need, std::min<int64_t>(b.rows * b.cols, int64_t(4) << 20));
+            need = std::max<int64_t>(need, b.cols);
+        }
+    }
+    return need;
+}
+
+size_t region_bytes(int64_t n, int64_t m, int precision) {
+    const size_t sz = elem_bytes(precision);
+    return align256(REGION_HDR + (size_t)NXV * round_up(n, XY_ALIGN) * sz +
+                    (size_t)NYV * round_up(m, XY_ALIGN) * sz);
+}
+
+size_t op_dev_bytes(const cgs_op& op, int precision) {
+    const size_t sz = elem_bytes(precision);
+    size_t tot = 0;
+    for (const auto& b : op.blocks) {
+        if (b.kind == CGS_BLOCK_CONV) tot += 2 * align256(round_up(b.k, conv_r(precision)) * sz);
+        if (b.kind == CGS_BLOCK_DENSE) {
+            const size_t ld = dense_ld(b.cols), ldt = dense_ld(b.rows);
+            tot += align256(b.rows * ld * sz) + align256(b.cols * ldt * sz);
+            if (precision == CGS_BF16) tot += align256(b.rows * ld * 2) + align256(b.cols * ldt * 2);
+        }
+    }
+    return tot;
+}
+
+void op_dev_shape(const cgs_op& op, int precision, OpDev* out) {
+    out->ids.clear();
+    out->convs.clear();
+    out->dense.clear();
+    for (const auto& b : op.blocks) {
+        if (b.kind == CGS_BLOCK_IDENTITY) {
+            out->ids.push_back(IdBlock{b.row0, b.col0, b.rows, b.scale});
+        } else if (b.kind == CGS_BLOCK_CONV) {
+            ConvBlock cb{};
+            cb.row0 = b.row0;
+            cb.col0 = b.col0;
+            cb.n_in = b.n_in;
+            cb.k = b.k;
+            cb.kpad = round_up(b.k, conv_r(precision));
+            cb.scale = b.scale;
+            out->convs.push_back(cb);
+        } else {
+            DenseBlock db{};
+            db.row0 = b.row0;
+            db.col0 = b.col0;
+            db.rows = b.rows;
+            db.cols = b.cols;
+            db.ld = dense_ld(b.cols);
+            db.ldt = dense_ld(b.rows);
+            db.scale = b.scale;
+            out->dense.push_back(db);
+        }
+    }
+}
+
+int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hipStream_t st,
+              OpDev* out) {
+    op_dev_shape(op, precision, out);
+    const int prec = work_prec(precision);
+    const size_t sz = elem_bytes(precision);
+    char* p = dst;
+    size_t ci = 0, di = 0;
+    for (const auto& b : op.blocks) {
+        if (b.kind == CGS_BLOCK_CONV) {
+            ConvBlock& cb = out->convs[ci++];
+            const int64_t kpad = cb.kpad, k = cb.k;
+            if (2 * kpad > stg.cap) return fail(CGS_ENOMEM, "staging too small for %lld taps", (long long)k);
+            for (int64_t t = 0; t < kpad; ++t) {
+                stg.host[t] = t < k ? b.data[k - 1 - t] : 0.0;   // correlation order of A x
+                stg.host[kpad + t] = t < k ? b.data[t] : 0.0;    // correlation order of A^T y
+            }
+            CGS_HIP(hipMemcpyAsync(stg.dev, stg.host, 2 * kpad * sizeof(double), hipMemcpyHostToDevice, st));
+            cb.w_fwd = p;
+            launch_cast(prec, stg.dev, p, kpad, st);
+            p += align256(kpad * sz);
+            cb.w_adj = p;
+            launch_cast(prec, stg.dev + kpad, p, kpad, st);
+            p += align256(kpad * sz);
+            CGS_HIP(hipStreamSynchronize(st));
+        } else if (b.kind == CGS_BLOCK_DENSE) {
+            DenseBlock& db = out->dense[di++];
+            const int64_t rows = db.rows, cols = db.cols, ld = db.ld, ldt = db.ldt;
+            db.a = p;
+            p += align256(rows * ld * sz);
+            db.at = p;
+            p += align256(cols * ldt * sz);
+            CGS_HIP(hipMemsetAsync(const_cast<void*>(db.at), 0, cols * ldt * sz, st));
+            const int64_t rpc = std::max<int64_t>(1, stg.cap / cols);
+            for (int64_t r0 = 0; r0 < rows; r0 += rpc) {
+                const int64_t nr = std::min(rpc, rows - r0);
+                std::memcpy(stg.host, b.data.data() + r0 * cols, (size_t)(nr * cols) * sizeof(double));
+                CGS_HIP(hipMemcpyAsync(stg.dev, stg.host, (size_t)(nr * cols) * sizeof(double),
+                                       hipMemcpyHostToDevice, st));
+                launch_cast_pad(prec, stg.dev, nr, cols, (char*)db.a + r0 * ld * sz, ld, st);
+                launch_cast_transpose(prec, stg.dev, nr, cols, const_cast<void*>(db.at), ldt, r0, st);
+                CGS_HIP(hipStreamSynchronize(st));
+            }
+            if (precision == CGS_BF16) {
+                db.a16 = p;
+                p += align256(rows * ld * 2);
+                db.at16 = p;
+                p += align256(cols * ldt * 2);
+                launch_to_bf16((const float*)db.a, (uint16_t*)db.a16, rows * ld, st);
+                launch_to_bf16((const float*)db.at, (uint16_t*)db.at16, cols * ldt, st);
+            }
+        }
+    }
+    CGS_HIP(hipGetLastError());
+    CGS_HIP(hipStreamSynchronize(st));
+    return CGS_OK;
+}
+
+int upload_f64(const Staging& stg, hipStream_t st, const double* src, int64_t n, int prec, void* dst) {
+    const size_t sz = prec == 0 ? 8 : 4;
+    for (int64_t off = 0; off < n; off += stg.cap) {
+        const int64_t c = std::min(stg.cap, n - off);
+        std::memcpy(stg.host, src + off, (size_t)c * sizeof(double));
+        CGS_HIP(hipMemcpyAsync(stg.dev, stg.host, (size_t)c * sizeof(double), hipMemcpyHostToDevice, st));
+        launch_cast(prec, stg.dev, (char*)dst + off * sz, c, st);
+        CGS_HIP(hipGetLastError());
+        CGS_HIP(hipStreamSynchronize(st));
+    }
+    return CGS_OK;
+}
+
+int download_f64(const Staging& stg, hipStream_t st, int prec, const void* src, int64_t n, double* dst) {
+    const size_t sz = prec == 0 ? 8 : 4;
+    for (int64_t off = 0; off < n; off += stg.cap) {
+        const int64_t c = std::min(stg.cap, n - off);
+        launch_cast_back(prec, (const char*)src + off * sz, stg.dev, c, st);
+        CGS_HIP(hipGetLastError());
+        CGS_HIP(hipMemcpyAsync(stg.host, stg.dev, (size_t)c * sizeof(double), hipMemcpyDeviceToHost, st));
+        CGS_HIP(hipStreamSynchronize(st));
+        std::memcpy(dst + off, stg.host, (size_t)c * sizeof(double));
+    }
+    return CGS_OK;
+}
+
+// ---------------------------------------------------------------- tables
+void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im) {
+    im = TableImage{};
+    const int64_t ct = conv_tile(precision);
+    for (size_t i = 0; i < recs.size(); ++i) {
+        const InstRec& r = recs[i];
+        const int ii = (int)i;
+        InstDesc d{};
+        d.base = r.base;
+        d.n = r.n;
+        d.m = r.m;
+        d.nxs = round_up(r.n, XY_ALIGN);
+        d.nys = round_up(r.m, XY_ALIGN);
+        d.l = r.l;
+        d.xt0 = (int32_t)im.xt.size();
+        for (int64_t s = 0; s < r.n; s += VEC_TILE)
+            im.xt.push_back(VecTile{ii, -1, s, (int32_t)std::min<int64_t>(VEC_TILE, r.n - s), 0});
+        d.xt1 = (int32_t)im.xt.size();
+        d.yt0 = (int32_t)im.yt.size();
+        for (int64_t s = 0; s < r.l; s += VEC_TILE)
+            im.yt.push_back(VecTile{ii, -1, s, (int32_t)std::min<int64_t>(VEC_TILE, r.l - s), 0});
+        d.sg0 = (int32_t)im.seg.size();
+        int64_t off = r.l;
+        for (int64_t qj : r.q) {
+            SocSeg sg{};
+            sg.inst = ii;
+            sg.yt0 = (int32_t)im.yt.size();
+            sg.start = off;
+            sg.len = qj;
+            const int32_t sid = (int32_t)im.seg.size();
+            for (int64_t s = 0; s < qj; s += VEC_TILE)
+                im.yt.push_back(VecTile{ii, sid, off + s, (int32_t)std::min<int64_t>(VEC_TILE, qj - s), 0});
+            sg.ntiles = (int32_t)im.yt.size() - sg.yt0;
+            im.seg.push_back(sg);
+            off += qj;
+        }
+        d.sg1 = (int32_t)im.seg.size();
+        d.yt1 = (int32_t)im.yt.size();
+        d.id0 = (int32_t)im.ids.size();
+        for (const IdBlock& b : r.op->ids) im.ids.push_back(b);
+        d.id1 = (int32_t)im.ids.size();
+        for (size_t j = 0; j < r.op->convs.size(); ++j) {
+            if (im.cfwd.size() <= j) {
+                im.cfwd.resize(j + 1);
+                im.cadj.resize(j + 1);
+            }
+            const ConvBlock& cb = r.op->convs[j];
+            const int32_t bi = (int32_t)im.cblk.size();
+            im.cblk.push_back(cb);
+            const int64_t n_out = cb.n_in + cb.k - 1;
+            for (int64_t s = 0; s < n_out; s += ct) im.cfwd[j].push_back(ConvTile{ii, bi, s});
+            for (int64_t s = 0; s < cb.n_in; s += ct) im.cadj[j].push_back(ConvTile{ii, bi, s});
+        }
+        for (size_t j = 0; j < r.op->dense.size(); ++j) {
+            if (im.dfwd.size() <= j) {
+                im.dfwd.resize(j + 1);
+                im.dadj.resize(j + 1);
+            }
+            const DenseBlock& db = r.op->dense[j];
+            const int32_t bi = (int32_t)im.dblk.size();
+            im.dblk.push_back(db);
+            for (int64_t s = 0; s < db.rows; s += DENSE_ROWS)
+                im.dfwd[j].push_back(DenseTile{ii, bi, s, (int32_t)std::min<int64_t>(DENSE_ROWS, db.rows - s), 0});
+            for (int64_t s = 0; s < db.cols; s += DENSE_ROWS)
+                im.dadj[j].push_back(DenseTile{ii, bi, s, (int32_t)std::min<int64_t>(DENSE_ROWS, db.cols - s), 0});
+        }
+        im.inst.push_back(d);
+    }
+}
+
+template <typename V>
+static size_t vbytes(const std::vector<V>& v) { return align256(v.size() * sizeof(V)); }
+
+size_t image_table_bytes(const TableImage& im) {
+    size_t t = vbytes(im.inst) + vbytes(im.xt) + vbytes(im.yt) + vbytes(im.seg) + vbytes(im.ids) +
+               vbytes(im.cblk) + vbytes(im.dblk);
+    for (const auto& v : im.cfwd) t += vbytes(v);
+    for (const auto& v : im.cadj) t += vbytes(v);
+    for (const auto& v : im.dfwd) t += vbytes(v);
+    for (const auto& v : im.dadj) t += vbytes(v);
+    return t + 256;
+}
+
+size_t image_work_bytes(const TableImage& im) {
+    return align256(4 * im.xt.size() * 8) + align256(4 * im.yt.size() * 8) +
+           align256(2 * im.seg.size() * 8) + align256(im.seg.size() * 4) +
+           align256(im.inst.size() * NSC * 8) + 256;
+}
+
+// ---------------------------------------------------------------- engine
+Engine::~Engine() {
+    drop_graph();
+    if (tab_host) (void)hipHostFree(tab_host);
+    if (scal_host) (void)hipHostFree(scal_host);
+    if (stg.host) (void)hipHostFree(stg.host);
+}
+
+void Engine::drop_graph() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    graph_exec = nullptr;
+    graph = nullptr;
+    graph_steps = -1;
+}
+
+int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles) {
+    CGS_HIP(hipHostMalloc((void**)&tab_host, std::max<size_t>(tab_bytes, 256), hipHostMallocDefault));
+    tab_host_cap = tab_bytes;
+    CGS_HIP(hipHostMalloc((void**)&scal_host, std::max<size_t>(1, (size_t)max_inst) * NSC * sizeof(double),
+                          hipHostMallocDefault));
+    scal_host_cap = max_inst;
+    CGS_HIP(hipHostMalloc((void**)&stg.host, (size_t)stg_doubles * sizeof(double), hipHostMallocDefault));
+    stg.cap = stg_doubles;
+    return CGS_OK;
+}
+
+int Engine::build(const std::vector<InstRec>& r) {
+    recs = r;
+    build_image(recs, precision, im);
+    const size_t tb = image_table_bytes(im), wb = image_work_bytes(im);
+    if (tb > tab_cap || tb > tab_host_cap || wb > work_cap || (int)im.inst.size() > scal_host_cap)
+        return fail(CGS_ENOMEM, "tile tables need %zu + %zu bytes (have %zu + %zu)", tb, wb, tab_cap, work_cap);
+    CGS_HIP(hipStreamSynchronize(stream));
+    size_t off = 0;
+    auto put = [&](const void* src, size_t bytes) -> char* {
+        if (bytes) std::memcpy(tab_host + off, src, bytes);
+        char* d = tab_dev + off;
+        off += align256(bytes);
+        return d;
+    };
+    inst_dev = (InstDesc*)put(im.inst.data(), im.inst.size() * sizeof(InstDesc));
+    T.inst = inst_dev;
+    T.xt = (const VecTile*)put(im.xt.data(), im.xt.size() * sizeof(VecTile));
+    T.yt = (const VecTile*)put(im.yt.data(), im.yt.size() * sizeof(VecTile));
+    T.seg = (const SocSeg*)put(im.seg.data(), im.seg.size() * sizeof(SocSeg));
+    T.ids = (const IdBlock*)put(im.ids.data(), im.ids.size() * sizeof(IdBlock));
+    const ConvBlock* cbd = (const ConvBlock*)put(im.cblk.data(), im.cblk.size() * sizeof(ConvBlock));
+    const DenseBlock* dbd = (const DenseBlock*)put(im.dblk.data(), im.dblk.size() * sizeof(DenseBlock));
+    cf.clear(); ca.clear(); df.clear(); da.clear();
+    for (const auto& v : im.cfwd) cf.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size()});
+    for (const auto& v : im.cadj) ca.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size()});
+    for (const auto& v : im.dfwd) df.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
+    for (const auto& v : im.dadj) da.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
+    if (off > tab_cap) return fail(CGS_ENOMEM, "table overflow");
+    CGS_HIP(hipMemcpyAsync(tab_dev, tab_host, off, hipMemcpyHostToDevice, stream));
+    char* w = work_dev;
+    T.xpart = (double*)w; w += align256(4 * im.xt.size() * 8);
+    T.ypart = (double*)w; w += align256(4 * im.yt.size() * 8);
+    T.seg_val = (double*)w; w += align256(2 * im.seg.size() * 8);
+    T.seg_cnt = (int*)w; w += align256(im.seg.size() * 4);
+    gather_dev = (double*)w;
+    if (!im.seg.empty()) CGS_HIP(hipMemsetAsync(T.seg_cnt, 0, im.seg.size() * 4, stream));
+    T.nx_tiles = (int)im.xt.size();
+    T.ny_tiles = (int)im.yt.size();
+    T.nseg = (int)im.seg.size();
+    T.ninst = (int)im.inst.size();
+    CGS_HIP(hipStreamSynchronize(stream));
+    drop_graph();
+    return CGS_OK;
+}
+
+char* Engine::xptr(int i, int kind) const {
+    const InstDesc& d = im.inst[i];
+    return d.base + REGION_HDR + (size_t)kind * d.nxs * elem_bytes(precision);
+}
+char* Engine::yptr(int i, int kind) const {
+    const InstDesc& d = im.inst[i];
+    return d.base + REGION_HDR + ((size_t)NXV * d.nxs + (size_t)kind * d.nys) * elem_bytes(precision);
+}
+
+void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
+    launch_apply_init(prec, T, adj, out, in, base, sigma, gate, stream);
+    for (const auto& c : adj ? ca : cf) launch_conv(prec, T, c, adj, out, in, sigma, gate, stream);
+    for (const auto& d : adj ? da : df) launch_gemv(prec, T, d, adj, out, in, sigma, gate, stream);
+}
+
+// One CG iteration of the Section IV-B listing on (I + A^T A):
+// q = p + A^T (A p); alpha = rr/<p,q>; z += alpha p; r -= alpha q; beta; p = r + beta p.
+void Engine::cg_iter(int z, int gate, int cg_max) {
+    apply(0, YT, XP, -1, 1.0, gate);
+    apply(1, XQ, YT, XP, 1.0, gate);
+    launch_cg_dot(prec, T, XP, XQ, gate, stream);
+    launch_cg_update(prec, T, z, XR, XP, XQ, cg_max, gate, stream);
+    launch_cg_dir(prec, T, XR, XP, gate, stream);
+}
+
+// One ADMM step of the homogeneous self-dual embedding.
+void Engine::admm_step() {
+    launch_wy(prec, T, G_ADMM, stream);                        // w_y = u_y + v_s
+    apply(1, XH, YW, XU, -1.0, G_ADMM);                          // h = u_x - A^T w_y
+    apply(0, YT, XZ, -1, 1.0, G_ADMM);                           // q = z + A^T A z (warm start)
+    apply(1, XQ, YT, XZ, 1.0, G_ADMM);
+    launch_cg_init(prec, T, XZ, XR, XP, XQ, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
+                   st.cg_max_iters, G_ADMM, stream);
+    for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters);
+    apply(0, YZ, XZ, YW, 1.0, G_ADMM);                           // z_y = w_y + A z_x
+    launch_tau_dots(prec, T, st.alpha, stream);                  // u~_tau, tau, kappa
+    launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
+    launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
+}
+
+void Engine::check() {
+    apply(0, YT, XU, -1, 1.0, G_CHECK);                          // A u_x
+    apply(1, XT, YU, -1, 1.0, G_CHECK);                          // A^T u_y
+    launch_resid(prec, T, st.eps, st.max_iters, stream);
+}
+
+int Engine::round(int nsteps) {
+    const bool use_g = st.use_graph && stream != nullptr && nsteps == st.check_every;
+    if (use_g) {
+        if (!graph_exec || graph_steps != nsteps) {
+            drop_graph();
+            CGS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < nsteps; ++i) admm_step();
+            check();
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(stream, &g);
+            if (e != hipSuccess) return fail(CGS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+            graph = g;
+            CGS_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
+            graph_steps = nsteps;
+        }
+        CGS_HIP(hipGraphLaunch(graph_exec, stream));
+    } else {
+        for (int i = 0; i < nsteps; ++i) admm_step();
+        check();
+    }
+    CGS_HIP(hipGetLastError());
+    return CGS_OK;
+}
+
+int Engine::fetch_scalars() {
+    launch_gather_scalars(inst_dev, T.ninst, gather_dev, stream);
+    CGS_HIP(hipGetLastError());
+    CGS_HIP(hipMemcpyAsync(scal_host, gather_dev, (size_t)T.ninst * NSC * sizeof(double),
+                           hipMemcpyDeviceToHost, stream));
+    CGS_HIP(hipStreamSynchronize(stream));
+    return CGS_OK;
+}
+
+int Engine::setup() {
+    launch_norms(prec, T, G_SETUP, stream);
+    apply(1, XH, YB, XC, -1.0, G_SETUP);                          // h = c - A^T b
+    launch_cg_init(prec, T, XG, XR, XP, XQ, XH, 0, 0.0, 0.0, st.setup_tol, st.setup_max_iters,
+                   G_SETUP, stream);
+    int it = 0;
+    while (it < st.setup_max_iters) {
+        const int nb = std::min(8, st.setup_max_iters - it);
+        for (int j = 0; j < nb; ++j) cg_iter(XG, G_SETUP_CG, st.setup_max_iters);
+        it += nb;
+        CGS_TRY(fetch_scalars());
+        bool any = false;
+        for (int i = 0; i < T.ninst; ++i) {
+            const double* sc = scalars(i);
+            if (sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0 && sc[SC_CGACT] != 0.0) any = true;
+        }
+        if (!any) break;
+    }
+    apply(0, YG, XG, YB, 1.0, G_SETUP);                           // g_y = b + A g_x
+    launch_eta(prec, T, stream);                                  // eta; phase -> 1
+    CGS_HIP(hipGetLastError());
+    return CGS_OK;
+}
+
+int Engine::reset(int inst) {
+    launch_reset(prec, T, inst, stream);
+    CGS_HIP(hipGetLastError());
+    return CGS_OK;
+}
+
+int Engine::set_scalar(int inst, int slot, double v) {
+    launch_set_scalar(inst_dev, inst, slot, v, stream);
+    CGS_HIP(hipGetLastError());
+    return CGS_OK;
+}
+
+void Engine::fill_info(int i, cgs_info* info) const {
+    const double* sc = scalars(i);
+    info->status = (int32_t)sc[SC_STATUS];
+    info->iters = (int32_t)sc[SC_ITER];
+    info->cg_iters = (int64_t)sc[SC_CGTOT];
+    info->tau = sc[SC_TAU];
+    info->kappa = sc[SC_KAPPA];
+    const double tau = sc[SC_TAU];
+    info->pobj = tau > 0.0 ? sc[SC_CUX] / tau : NAN;
+    info->dobj = tau > 0.0 ? -sc[SC_BUY] / tau : NAN;
+    info->res_pri = sc[SC_RP];
+    info->res_dual = sc[SC_RD];
+    info->gap = sc[SC_GAP];
+}
+
+}  // namespace cgs

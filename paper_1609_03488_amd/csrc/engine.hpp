@@ -1,0 +1,163 @@
+// Host side of the solver engine: operator descriptions, device layouts, tile
+// tables and the orchestration of the ADMM iteration on a HIP stream.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "cgs.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cgs {
+
+// ---------------------------------------------------------------- errors
+int fail(int code, const char* fmt, ...);
+const char* last_error();
+
+#define CGS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::cgs::fail(CGS_EHIP, "%s failed: %s (%s:%d)", #call,                 \
+                               hipGetErrorString(e_), __FILE__, __LINE__);              \
+    } while (0)
+#define CGS_TRY(expr)              \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != CGS_OK) return rc_; \
+    } while (0)
+
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline int work_prec(int precision) { return precision == CGS_FP64 ? 0 : 1; }
+inline size_t elem_bytes(int precision) { return precision == CGS_FP64 ? 8 : 4; }
+
+// ---------------------------------------------------------------- host operator
+struct HostBlock {
+    int kind;
+    int64_t row0, col0, rows, cols;
+    int64_t k, n_in;          // conv
+    double scale;
+    std::vector<double> data; // taps (k) or dense rows x cols (packed)
+};
+
+}  // namespace cgs
+
+struct cgs_op {
+    int64_t m, n;
+    std::vector<cgs::HostBlock> blocks;
+};
+
+namespace cgs {
+
+int validate_cone(int64_t m, int64_t l, const int64_t* q, int64_t nq);
+int validate_settings(const cgs_settings* st);
+
+// ---------------------------------------------------------------- staging
+// FP64 transfers go through a pinned host buffer and a device buffer of `cap`
+// doubles; conversion to the working precision happens on the device.
+struct Staging {
+    double* dev = nullptr;
+    double* host = nullptr;
+    int64_t cap = 0;
+};
+int64_t staging_doubles(const cgs_op& op, int64_t max_vec);
+
+// ---------------------------------------------------------------- device operator data
+struct OpDev {
+    std::vector<IdBlock> ids;
+    std::vector<ConvBlock> convs;
+    std::vector<DenseBlock> dense;
+};
+size_t op_dev_bytes(const cgs_op& op, int precision);
+// Metadata only (null data pointers): used to size tables.
+void op_dev_shape(const cgs_op& op, int precision, OpDev* out);
+int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hipStream_t st,
+              OpDev* out);
+
+// Bytes of one instance's region (scalars, counters, X and Y vectors).
+size_t region_bytes(int64_t n, int64_t m, int precision);
+
+int upload_f64(const Staging& stg, hipStream_t st, const double* src, int64_t n, int prec,
+               void* dst);
+int download_f64(const Staging& stg, hipStream_t st, int prec, const void* src, int64_t n,
+                 double* dst);
+
+// ---------------------------------------------------------------- instances and tables
+struct InstRec {
+    char* base = nullptr;
+    int64_t n = 0, m = 0, l = 0;
+    std::vector<int64_t> q;
+    const OpDev* op = nullptr;
+};
+
+struct TableImage {
+    std::vector<InstDesc> inst;
+    std::vector<VecTile> xt, yt;
+    std::vector<SocSeg> seg;
+    std::vector<IdBlock> ids;
+    std::vector<ConvBlock> cblk;
+    std::vector<std::vector<ConvTile>> cfwd, cadj;   // per conv slot
+    std::vector<DenseBlock> dblk;
+    std::vector<std::vector<DenseTile>> dfwd, dadj;  // per dense slot
+};
+void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im);
+size_t image_table_bytes(const TableImage& im);
+size_t image_work_bytes(const TableImage& im);
+
+// ---------------------------------------------------------------- engine
+class Engine {
+  public:
+    int precision = CGS_FP32;
+    int prec = 1;                 // element type selector of the kernels
+    cgs_settings st{};
+    hipStream_t stream = nullptr;
+
+    char* tab_dev = nullptr;  size_t tab_cap = 0;
+    char* work_dev = nullptr; size_t work_cap = 0;
+    char* tab_host = nullptr; size_t tab_host_cap = 0;   // pinned
+    double* scal_host = nullptr; int scal_host_cap = 0;   // pinned
+    Staging stg;
+
+    std::vector<InstRec> recs;
+    TableImage im;
+    Tables T{};
+    InstDesc* inst_dev = nullptr;
+    double* gather_dev = nullptr;
+    std::vector<ConvLaunch> cf, ca;
+    std::vector<DenseLaunch> df, da;
+    int cg_launch = 1;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = -1;
+
+    ~Engine();
+    int init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles);
+    // Build and upload the tile tables of `recs`.
+    int build(const std::vector<InstRec>& r);
+    void drop_graph();
+
+    // ---- device work (enqueue only)
+    void apply(int adj, int out, int in, int base, double sigma, int gate);
+    void cg_iter(int z, int gate, int cg_max);
+    void admm_step();
+    void check();
+    // ---- host loops
+    int setup();                  // instances with phase 0 (synchronises)
+    int round(int nsteps);        // nsteps ADMM steps + termination test (enqueue)
+    int fetch_scalars();          // gather per-instance scalars into scal_host (synchronises)
+    const double* scalars(int i) const { return scal_host + (size_t)i * NSC; }
+    int reset(int inst);          // inst < 0: all
+    int set_scalar(int inst, int slot, double v);
+    char* xptr(int inst, int kind) const;
+    char* yptr(int inst, int kind) const;
+    void fill_info(int i, cgs_info* info) const;
+};
+
+}  // namespace cgs

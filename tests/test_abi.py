@@ -1,0 +1,124 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and
+the host-side validation returns the documented error codes (no GPU calls)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cgs.h")
+
+P = pytest.importorskip("paper_1609_03488_amd")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cgs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = P.lib()
+    names = _declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    # and nm agrees (extern "C", default visibility)
+    syms = os.popen(f"nm -D --defined-only {P.library_path}").read()
+    for n in names:
+        assert re.search(rf"\bT {n}\b", syms), n
+
+
+def test_binding_covers_every_declared_function():
+    from paper_1609_03488_amd import _lib
+    assert set(_declared_functions()) == set(_lib._SIGS)
+
+
+def test_settings_defaults():
+    s = P.Settings.make()
+    assert s.eps == 1e-4 and s.alpha == 1.5 and s.precision == P.FP32
+    assert s.cg_max_iters >= 1 and s.check_every >= 1 and s.use_graph == 1
+
+
+def _ws(op, l, q, **kw):
+    lib = P.lib()
+    st = P.Settings.make(**kw)
+    qa = np.asarray(q, dtype=np.int64)
+    nb = C.c_size_t()
+    rc = lib.cgs_workspace_bytes(op._h, l, qa.ctypes.data_as(C.POINTER(C.c_int64)), len(q),
+                                 C.byref(st), 1, C.byref(nb))
+    return rc, nb.value
+
+
+def test_operator_validation_codes():
+    with pytest.raises(P.CgsError) as e:
+        P.Operator(0, 3)
+    assert e.value.code == -2
+    op = P.Operator(10, 4)
+    with pytest.raises(P.CgsError) as e:
+        op.add_identity(8, 0, 3)          # rows 8..10 exceed m
+    assert e.value.code == -2
+    with pytest.raises(P.CgsError) as e:
+        op.add_conv(0, 0, [1.0, np.nan], 4)
+    assert e.value.code == -1
+    with pytest.raises(P.CgsError) as e:
+        op.add_conv(0, 0, np.ones(8), 4)  # 11 rows > 10
+    assert e.value.code == -2
+    with pytest.raises(P.CgsError) as e:
+        op.add_dense(0, 0, np.full((2, 2), np.inf))
+    assert e.value.code == -1
+    op.add_conv(0, 0, np.ones(7), 4)
+    op.add_identity(0, 0, 4, -1.0)
+
+
+def test_workspace_and_cone_validation():
+    op = P.Operator(10, 4).add_conv(0, 0, np.ones(7), 4)
+    rc, nb = _ws(op, 5, [5])
+    assert rc == 0 and nb > 0
+    assert _ws(op, 5, [4])[0] == -3                 # cones cover 9 of 10 rows
+    assert _ws(op, 5, [0, 5])[0] == -3              # empty cone
+    assert _ws(op, 5, [5], eps=0.0)[0] == -1
+    assert _ws(op, 5, [5], alpha=2.0)[0] == -1
+    assert _ws(op, 5, [5], precision=7)[0] == -1
+    # more batch instances need more memory
+    rc1, nb1 = _ws(op, 10, [])
+    assert rc1 == 0
+
+
+def test_workspace_scales_with_precision_and_batch():
+    lib = P.lib()
+    op = P.Operator(1000, 400).add_dense(0, 0, np.ones((1000, 400)))
+    q = np.array([1000], dtype=np.int64)
+    out = {}
+    for prec in (P.FP64, P.FP32):
+        for batch in (1, 4):
+            st = P.Settings.make(precision=prec)
+            nb = C.c_size_t()
+            assert lib.cgs_workspace_bytes(op._h, 0, q.ctypes.data_as(C.POINTER(C.c_int64)), 1,
+                                           C.byref(st), batch, C.byref(nb)) == 0
+            out[prec, batch] = nb.value
+    assert out[P.FP64, 1] > out[P.FP32, 1]
+    assert out[P.FP32, 4] > out[P.FP32, 1]
+    # the shared dense block is stored once (plus its transpose), not per instance
+    assert out[P.FP32, 4] - out[P.FP32, 1] < 2 * 1000 * 400 * 4
+
+
+def test_canonical_forms_match_paper_dimensions():
+    """Table III (deconvolution) and Table II (lasso) problem sizes."""
+    for n0 in (100, 1000):
+        pr = P.deconv_problem(np.ones(n0) / n0, np.zeros(2 * n0 - 1))
+        assert (pr.op.n, pr.op.m) == (n0 + 1, 3 * n0)
+        assert pr.l + sum(pr.q) == pr.op.m
+    pr = P.lasso_problem(np.ones((60, 30)), np.zeros(60), 0.1)
+    assert (pr.op.n, pr.op.m) == (61, 122)
+    assert pr.op.kinds.count("dense") == 1
+
+
+def test_request_bytes_and_server_precision_check():
+    op = P.Operator(10, 4).add_conv(0, 0, np.ones(7), 4)
+    nb = P.Server.request_bytes(op, 5, [5], P.FP32)
+    assert nb >= 512
+    with pytest.raises(P.CgsError):
+        P.Server.request_bytes(op, 5, [5], P.BF16)

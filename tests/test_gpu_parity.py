@@ -1,0 +1,351 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every test prints its case name before touching the GPU.  Sizes span several
+tiles plus a ragged tail (vector tiles of 1024, convolution tiles of 1024/2048
+outputs, tap chunks of 256/512, dense tiles of 4 rows).
+"""
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1609_03488_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _solver(pr, precision, batch=1, **kw):
+    st = P.Settings.make(precision=precision, **kw)
+    s = P.Solver(pr.op, pr.l, pr.q, st, batch=batch)
+    return s
+
+
+def _cases():
+    out = []
+    d = w.deconv_instance(3000, 101, 15.0, 0.1, 1e-4, 11)
+    out.append(("deconv_n3000_k101", P.deconv_problem(d["c"], d["b"]),
+                o.deconv_program(d["c"], d["b"])))
+    d = w.deconv_instance(5000, 1025, 150.0, 0.01, 1e-6, 12)
+    out.append(("deconv_n5000_k1025", P.deconv_problem(d["c"], d["b"]),
+                o.deconv_program(d["c"], d["b"])))
+    d = w.lasso_instance(300, 700, 0.05, 1e-4, 13)
+    out.append(("lasso_300x700", P.lasso_problem(d["A"], d["b"], d["lam"]),
+                o.lasso_program(d["A"], d["b"], d["lam"])))
+    return out
+
+
+CASES = _cases()
+
+
+# ----------------------------------------------------------------- a2, a3: applies
+
+def _abs_bound(prog, v, adj):
+    """sum_j |a_ij| |v_j| per output (what floating-point error of the apply scales with)."""
+    v = np.abs(v)
+    if prog.family == "deconv":
+        n, c = prog.data["n"], np.abs(prog.data["c"])
+        if not adj:
+            return np.concatenate([v[:n], [v[n]], np.convolve(c, v[:n])])
+        return np.concatenate([v[:n] + np.correlate(v[n + 1:], c, "valid"), [v[n]]])
+    n, m0, A = prog.data["n"], prog.data["m"], np.abs(prog.data["A"])
+    if not adj:
+        xt = v[:n] + v[n:2 * n]
+        return np.concatenate([xt, xt, [v[2 * n]], 2 * (A @ v[:n]), [v[2 * n]]])
+    y12 = v[:n] + v[n:2 * n]
+    return np.concatenate([y12 + 2 * (A.T @ v[2 * n + 1:2 * n + 1 + m0]), y12,
+                           [v[2 * n] + v[-1]]])
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+@pytest.mark.parametrize("idx", range(len(CASES)))
+def test_forward_and_adjoint_apply(idx, prec):
+    """Elementwise: |dev - ref| <= (K + 4) u sum_j |a_ij||v_j|, with u the unit
+    roundoff of the working precision and K the number of terms accumulated in
+    that precision (convolution taps; the dense block accumulates in FP64)."""
+    name, pr, prog = CASES[idx]
+    _say("apply", name, prec)
+    s = _solver(pr, prec)
+    rng = np.random.default_rng(idx)
+    z = rng.standard_normal(prog.n)
+    y = rng.standard_normal(prog.m)
+    az = s.apply(z)
+    aty = s.apply(y, transpose=True)
+    ref_az, ref_aty = prog.A(z), prog.AT(y)
+    u = 2.0 ** -53 if prec == P.FP64 else 2.0 ** -24
+    K = prog.data.get("k", 4) + 4
+    bf, ba = _abs_bound(prog, z, False), _abs_bound(prog, y, True)
+    assert np.all(np.abs(az - ref_az) <= (K + 4) * u * bf + 1e-300)
+    assert np.all(np.abs(aty - ref_aty) <= (K + 4) * u * ba + 1e-300)
+    # adjoint identity on the device results
+    assert abs(az @ y - z @ aty) <= 4 * (K + 4) * u * (bf @ np.abs(y) + ba @ np.abs(z))
+
+
+def test_identity_kernel_conv_is_exact():
+    _say("conv k=1")
+    b = np.linspace(-1, 1, 2500)
+    pr = P.deconv_problem(np.array([1.0]), b)
+    s = _solver(pr, P.FP64)
+    z = np.concatenate([np.arange(2500.0), [3.0]])
+    out = s.apply(z)
+    np.testing.assert_array_equal(out[:2500], -np.arange(2500.0))
+    np.testing.assert_array_equal(out[2501:], -np.arange(2500.0))
+
+
+# ----------------------------------------------------------------- a4: CG
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+@pytest.mark.parametrize("idx", range(len(CASES)))
+def test_cg_matches_direct_solve(idx, prec):
+    name, pr, prog = CASES[idx]
+    _say("cg", name, prec)
+    s = _solver(pr, prec)
+    rng = np.random.default_rng(100 + idx)
+    r = rng.standard_normal(prog.n)
+    tol = 1e-12 if prec == P.FP64 else 1e-6
+    z, it = s.normal_solve(r, tol=tol, max_iters=500)
+    ref = prog.factor().solve(r)
+    err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
+    assert err < (1e-10 if prec == P.FP64 else 2e-5), err
+    assert 0 < it < 500
+    # warm start at the solution: no iteration needed
+    z2, it2 = s.normal_solve(r, z0=ref, tol=1e-6, max_iters=50)
+    assert it2 <= 1
+
+
+# ----------------------------------------------------------------- a5-a6: iterates
+
+def _iter_cases():
+    out = []
+    d = w.deconv_instance(1200, 31, 4.0, 0.1, 1e-4, 21)
+    out.append(("deconv_n1200_k31", P.deconv_problem(d["c"], d["b"]),
+                o.deconv_program(d["c"], d["b"])))
+    d = w.lasso_instance(120, 300, 0.05, 1e-4, 22)
+    out.append(("lasso_120x300", P.lasso_problem(d["A"], d["b"], d["lam"]),
+                o.lasso_program(d["A"], d["b"], d["lam"])))
+    # a generic program with a nonnegative block and several second-order cones
+    rng = np.random.default_rng(23)
+    m, n, l, q = 1500, 40, 500, [1, 3, 996]
+    A = rng.standard_normal((m, n)) / np.sqrt(m)
+    x0 = rng.standard_normal(n)
+    s0 = o.proj_cone(rng.standard_normal(m), l, q)
+    b = A @ x0 + s0
+    y0 = o.proj_cone(rng.standard_normal(m), l, q)
+    c = -A.T @ y0
+    op = P.Operator(m, n).add_dense(0, 0, A)
+    from paper_1609_03488_amd.problems import ConeProblem
+    out.append(("socp_1500x40", ConeProblem(op, l, q, b, c, n), o.dense_program(A, b, c, l, q)))
+    return out
+
+
+ITER_CASES = _iter_cases()
+
+
+@pytest.mark.parametrize("idx", range(len(ITER_CASES)))
+def test_admm_iterates_match_oracle(idx):
+    """FP64 with CG solved to 1e-13: after N steps the embedding state matches
+    the oracle (exact subspace solve) element by element."""
+    name, pr, prog = ITER_CASES[idx]
+    _say("iterates", name)
+    N = 25
+    s = _solver(pr, P.FP64, cg_tol=0.0, cg_floor=1e-13, cg_max_iters=60, setup_tol=1e-14,
+                setup_max_iters=2000)
+    s.set_data(0, pr.b, pr.c)
+    s.iterate(N)
+    ux, uy, tau, vs, kap = s.state(0)
+    ref = o.scs_solve(prog, eps=1e-300, max_iters=N)
+    rux, ruy, rtau, rvs, rkap = ref.u
+    scale = max(1.0, np.abs(rux).max(), np.abs(ruy).max(), np.abs(rvs).max())
+    for a, b_ in ((ux, rux), (uy, ruy), (vs, rvs)):
+        assert np.abs(a - b_).max() <= 1e-8 * scale
+    assert abs(tau - rtau) <= 1e-8 * max(1, rtau) and abs(kap - rkap) <= 1e-8 * max(1, rkap)
+    # cone membership and complementarity of the device iterate
+    assert o.in_cone(uy, prog.l, prog.q, 1e-12 * scale)
+    assert o.in_cone(vs, prog.l, prog.q, 1e-12 * scale)
+    assert abs(uy @ vs) <= 1e-9 * scale ** 2
+
+
+@pytest.mark.parametrize("idx", range(len(ITER_CASES)))
+def test_residuals_match_oracle(idx):
+    name, pr, prog = ITER_CASES[idx]
+    _say("residuals", name)
+    s = _solver(pr, P.FP64, cg_tol=0.0, cg_floor=1e-13, cg_max_iters=60, setup_tol=1e-14)
+    s.set_data(0, pr.b, pr.c)
+    s.iterate(15)
+    ux, uy, tau, vs, kap = s.state(0)
+    info = s.residuals()[0]
+    if tau == 0.0:   # the embedding can pass through tau = 0; ratios are then undefined
+        assert np.isinf(info["res_pri"]) and np.isinf(info["res_dual"])
+        s.iterate(7)
+        ux, uy, tau, vs, kap = s.state(0)
+        info = s.residuals()[0]
+    assert tau > 0.0
+    rp, rd, gap, pobj, dobj = o.scs.residuals(prog, ux, uy, tau, vs)
+    np.testing.assert_allclose([info["res_pri"], info["res_dual"], info["gap"]], [rp, rd, gap],
+                               rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose([info["pobj"], info["dobj"]], [pobj, dobj], rtol=1e-9, atol=1e-12)
+
+
+# ----------------------------------------------------------------- whole solves
+
+def _objective(prog, x):
+    if prog.family == "deconv":
+        return o.deconv_objective(prog.data["c"], prog.data["b_obs"], x[:prog.data["n"]])
+    return o.lasso_objective(prog.data["A"], prog.data["b_obs"], prog.data["lam"], x[:prog.data["n"]])
+
+
+@pytest.mark.parametrize("idx,prec,eps", [(0, P.FP64, 1e-4), (0, P.FP32, 1e-4),
+                                           (1, P.FP64, 1e-6), (1, P.FP32, 1e-4)])
+def test_solve_matches_oracle(idx, prec, eps):
+    """Same method, same tolerance: the natural objective of the GPU solution is
+    within 1e-4 (relative) of the oracle's, and the GPU point's residuals,
+    recomputed in FP64, meet the tolerance."""
+    name, pr, prog = ITER_CASES[idx]
+    _say("solve", name, prec, eps)
+    s = _solver(pr, prec, eps=eps, check_every=10)
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, y, sl = s.solution(0)
+    # residuals of the returned point, recomputed in FP64 by the oracle
+    rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+    assert max(rp, rd, gap) <= 1.05 * eps
+    ref = o.scs_solve(prog, eps=eps, check_every=10)
+    f, fr = _objective(prog, x), _objective(prog, ref.x)
+    assert abs(f - fr) / abs(fr) <= 1e-4, (f, fr)
+
+
+def test_status_outcomes():
+    _say("status")
+    # infeasible: x >= 1 and x <= 0
+    op = P.Operator(2, 1).add_dense(0, 0, np.array([[-1.0], [1.0]]))
+    s = P.Solver(op, 2, [], P.Settings.make(precision=P.FP64, eps=1e-7, check_every=1, max_iters=50000))
+    s.set_data(0, np.array([-1.0, 0.0]), np.array([0.0]))
+    assert s.solve()[0]["status"] == P.INFEASIBLE
+    _, y, _ = s.solution(0)
+    assert np.all(y >= -1e-9) and -1.0 * y[0] + 0.0 * y[1] < 0
+    # unbounded: minimise -x, x >= 0
+    op = P.Operator(1, 1).add_dense(0, 0, np.array([[-1.0]]))
+    s = P.Solver(op, 1, [], P.Settings.make(precision=P.FP64, eps=1e-7, check_every=1, max_iters=50000))
+    s.set_data(0, np.array([0.0]), np.array([-1.0]))
+    assert s.solve()[0]["status"] == P.UNBOUNDED
+    x, _, _ = s.solution(0)
+    assert x[0] > 0 and abs(-x[0] + 1.0) < 1e-6
+    # iteration limit
+    name, pr, prog = ITER_CASES[0]
+    s = _solver(pr, P.FP32, max_iters=1, check_every=1)
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.MAX_ITERS and info["iters"] == 1
+    # non-finite data are rejected before any device work
+    with pytest.raises(P.CgsError) as e:
+        s.set_data(0, np.full(pr.op.m, np.nan), pr.c)
+    assert e.value.code == -1
+
+
+def test_warm_start_resumes():
+    name, pr, prog = ITER_CASES[1]
+    _say("warm start", name)
+    s = _solver(pr, P.FP64, cg_tol=0.0, cg_floor=1e-13, cg_max_iters=60, setup_tol=1e-14)
+    s.set_data(0, pr.b, pr.c)
+    s.iterate(10)
+    st = s.state(0)
+    s.iterate(10)
+    a = s.state(0)
+    s2 = _solver(pr, P.FP64, cg_tol=0.0, cg_floor=1e-13, cg_max_iters=60, setup_tol=1e-14)
+    s2.set_data(0, pr.b, pr.c)
+    s2.set_state(0, st[0], st[1], st[2], st[3], st[4])
+    s2.iterate(10)
+    b_ = s2.state(0)
+    np.testing.assert_allclose(a[0], b_[0], atol=1e-9)
+    np.testing.assert_allclose(a[1], b_[1], atol=1e-9)
+
+
+# ----------------------------------------------------------------- batch and server
+
+def test_batch_instances_equal_single_solves():
+    _say("batch")
+    A = w.lasso_matrix(150, 400, 31)
+    insts = [w.lasso_instance(150, 400, 0.05, 1e-4, 3100 + i, A=A, matrix_seed=31) for i in range(3)]
+    prs = [P.lasso_problem(A, d["b"], d["lam"]) for d in insts]
+    st = dict(eps=1e-5, check_every=10)
+    sb = _solver(prs[0], P.FP32, batch=3, **st)
+    for i, pr in enumerate(prs):
+        sb.set_data(i, pr.b, pr.c)
+    infos = sb.solve()
+    for i, pr in enumerate(prs):
+        s1 = _solver(pr, P.FP32, **st)
+        s1.set_data(0, pr.b, pr.c)
+        i1 = s1.solve()[0]
+        assert infos[i]["status"] == P.SOLVED and i1["status"] == P.SOLVED
+        assert infos[i]["iters"] == i1["iters"]
+        np.testing.assert_array_equal(sb.solution(i)[0], s1.solution(0)[0])
+
+
+def test_server_result_same_alone_and_in_mix():
+    _say("server alone vs mix")
+    reqs = [w.deconv_instance(n, k, k / 7.0, 0.05, 1e-4, 4000 + n) for n, k in
+            ((1500, 41), (3700, 101), (900, 11), (2600, 65))]
+    prs = [P.deconv_problem(d["c"], d["b"]) for d in reqs]
+    st = P.Settings.make(precision=P.FP32, eps=1e-4, check_every=10)
+    alone = []
+    for pr in prs:
+        sv = P.Server(64 << 20, 8, st)
+        t = sv.submit(pr.op, pr.l, pr.q, pr.b, pr.c)
+        while sv.step(50):
+            pass
+        alone.append(sv.fetch(t))
+        sv.close()
+    sv = P.Server(64 << 20, 8, st)
+    tickets = {}
+    tickets[0] = sv.submit(prs[0].op, prs[0].l, prs[0].q, prs[0].b, prs[0].c)
+    sv.step(30)
+    tickets[1] = sv.submit(prs[1].op, prs[1].l, prs[1].q, prs[1].b, prs[1].c)
+    tickets[2] = sv.submit(prs[2].op, prs[2].l, prs[2].q, prs[2].b, prs[2].c)
+    sv.step(20)
+    tickets[3] = sv.submit(prs[3].op, prs[3].l, prs[3].q, prs[3].b, prs[3].c)
+    mixed = {}
+    while len(mixed) < 4:
+        sv.step(10)
+        for i, t in tickets.items():
+            if i not in mixed and sv.poll(t) != P.RUNNING:
+                mixed[i] = sv.fetch(t)
+    for i in range(4):
+        xa, _, _, ia = alone[i]
+        xm, _, _, im = mixed[i]
+        assert ia["status"] == P.SOLVED and im["status"] == P.SOLVED
+        assert ia["iters"] == im["iters"]
+        np.testing.assert_array_equal(xa, xm)
+
+
+def test_server_admission_by_memory():
+    _say("server admission")
+    d = w.deconv_instance(20000, 101, 15.0, 0.05, 1e-4, 77)
+    pr = P.deconv_problem(d["c"], d["b"])
+    need = P.Server.request_bytes(pr.op, pr.l, pr.q, P.FP32)
+    sv = P.Server(24 << 20, 64, P.Settings.make(precision=P.FP32))
+    used, free = sv.usage()
+    assert used == 0
+    fits = free // need
+    assert fits >= 1
+    tickets = [sv.submit(pr.op, pr.l, pr.q, pr.b, pr.c) for _ in range(fits)]
+    assert all(t is not None for t in tickets)
+    assert sv.submit(pr.op, pr.l, pr.q, pr.b, pr.c) is None      # refused: no memory
+    sv.cancel(tickets[0])
+    assert sv.submit(pr.op, pr.l, pr.q, pr.b, pr.c) is not None  # memory came back
+    # slot limit
+    sv2 = P.Server(64 << 20, 1, P.Settings.make(precision=P.FP32))
+    assert sv2.submit(pr.op, pr.l, pr.q, pr.b, pr.c) is not None
+    assert sv2.submit(pr.op, pr.l, pr.q, pr.b, pr.c) is None
