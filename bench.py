@@ -1,19 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the structured-operator conic solver on one MI355X.
 
-A *step* is one complete solve of the large nonnegative deconvolution
-(n = 2^20 signal, 1025-tap Gaussian kernel, Section V-C, eq. 6) to the 1e-4
-relative KKT tolerance: setup (embedding vector by CG), then HSDE ADMM steps
-(CG on I + A^T A with the convolution and its adjoint, SOC / nonnegative
-projections, residual checks) until res_pri, res_dual and gap are <= 1e-4.
-The problem data are resident in HBM before the timed region; each step
-restarts the iterates on the device (no host transfer).
+Default workload (`deconv_n1M_k1025`): a *step* is one complete solve of the
+large nonnegative deconvolution (n = 2^20 signal, 1025-tap Gaussian kernel,
+Section V-C, eq. 6) to the 1e-4 relative KKT tolerance: setup (embedding vector
+by CG), then HSDE ADMM steps (CG on I + A^T A with the convolution and its
+adjoint, SOC / nonnegative projections, residual checks) until res_pri,
+res_dual and gap are <= 1e-4.  Problem data are resident in HBM before the
+timed region; each step restarts the iterates on the device.
+
+Other workloads (`--workload`): `deconv_n1000_k101` (FP64, 1e-6),
+`lasso_5000x10000` (FP32 dense lasso), `lasso_batch64_2000x8000` (64 lasso
+instances sharing A, BF16 MFMA GEMMs; a step solves all 64), and
+`serve_deconv_2000req` (replay of the 2000-request Poisson trace through the
+continuous-batching server; one step = the whole replay).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -24,41 +29,326 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-4 KKT residual & CG matvecs/s; batched solves/s, p50/p99 latency"
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published dense FP32 vector peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
+PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, data, gpu_iters: int, n_iter: int):
-    """FP64 oracle on this host: banded Cholesky + embedding setup + n_iter ADMM
-    iterations, extrapolated to the GPU's iteration count."""
-    import numpy as np
-    import oracle
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()]))
     except Exception:
-        threads = os.cpu_count()
-    prog = oracle.deconv_program(data["c"], data["b"])
+        return os.cpu_count()
+
+
+def timed_solves(s, steps, warmup, label):
+    import torch
+    for i in range(warmup):
+        s.reset()
+        info = s.solve()
+        log(f"{label} warmup {i}: {info[0]['status_name']} iters={info[0]['iters']} "
+            f"cg={info[0]['cg_iters']} t={info[0]['setup_s'] + info[0]['solve_s']:.3f}s")
+    torch.cuda.synchronize()
+    infos = []
     t0 = time.perf_counter()
-    fac = prog.factor()
-    t1 = time.perf_counter()
-    res = oracle.scs_solve(prog, eps=cfg["eps"], max_iters=n_iter, check_every=10, fac=fac)
-    t_factor = t1 - t0
-    t_setup = res.setup_s
-    t_iter = res.solve_s / max(res.iters, 1)
-    t_solve = t_factor + t_setup + gpu_iters * t_iter
+    for _ in range(steps):
+        s.reset()
+        infos.append(s.solve())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for i, inf in enumerate(infos):
+        log(f"{label} step {i}: {inf[0]['status_name']} iters={inf[0]['iters']} cg={inf[0]['cg_iters']} "
+            f"res=({inf[0]['res_pri']:.2e},{inf[0]['res_dual']:.2e},{inf[0]['gap']:.2e})")
+    return infos, elapsed
+
+
+def base_record(args, value, unit, elapsed, dtype, config):
     return {
-        "value": 1.0 / t_solve,
-        "unit": "solves/s",
-        "cores": int(threads),
-        "kind": "oracle",
-        "sample": (f"FP64 banded-Cholesky SCS oracle on the same problem: factorisation "
-                   f"{t_factor:.1f} s + embedding setup {t_setup:.1f} s + {res.iters} ADMM "
-                   f"iterations ({t_iter:.2f} s each) timed, extrapolated to the GPU's "
-                   f"{gpu_iters} iterations -> {t_solve:.0f} s per solve"),
+        "metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * elapsed / max(args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic", "config": config,
     }
+
+
+# ---------------------------------------------------------------- deconvolution (single)
+def run_deconv(args, cfg):
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1609_03488_amd as P
+
+    data = w.make_deconv(cfg)
+    n, k = cfg["n"], cfg["k"]
+    pr = P.deconv_problem(data["c"], data["b"])
+    stream = torch.cuda.Stream()
+    prec = P.FP64 if cfg["precision"] == "fp64" else P.FP32
+    st = P.Settings.make(precision=prec, eps=cfg["eps"], check_every=10)
+    if args.max_iters:
+        st.max_iters = args.max_iters
+    s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
+    s.set_data(0, pr.b, pr.c)
+    log(f"workspace {s.workspace_bytes / 2**20:.1f} MiB")
+    infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
+    last = infos[-1][0]
+    t_fwd = s.kernel_time(0, 20)
+    t_adj = s.kernel_time(1, 20)
+    flop_fwd, flop_adj = 2.0 * k * (n + k - 1), 2.0 * k * n
+    achieved = (flop_fwd + flop_adj) / ((t_fwd + t_adj) * 1e-3) / 1e12
+    log(f"conv A {t_fwd * 1e3:.1f} us, A^T {t_adj * 1e3:.1f} us, {achieved:.1f} TFLOP/s")
+    verify = None
+    if not args.no_verify:
+        import oracle
+        x, y, sl = s.solution(0)
+        prog = oracle.deconv_program(data["c"], data["b"])
+        rp, rd, gap, _, _ = oracle.scs.residuals(prog, x, y, 1.0, sl)
+        f = oracle.deconv_objective(data["c"], data["b"], x[:n])
+        noise = float(np.linalg.norm(data["b"] - np.convolve(data["c"], data["x_true"])))
+        verify = {"res_pri_fp64": rp, "res_dual_fp64": rd, "gap_fp64": gap, "objective": f,
+                  "objective_upper_bound_noise_norm": noise}
+        log("verify", verify)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        prog = oracle.deconv_program(data["c"], data["b"])
+        t0 = time.perf_counter()
+        fac = prog.factor()
+        t_factor = time.perf_counter() - t0
+        res = oracle.scs_solve(prog, eps=cfg["eps"], max_iters=args.cpu_iters, check_every=10, fac=fac)
+        t_iter = res.solve_s / max(res.iters, 1)
+        t_solve = t_factor + res.setup_s + last["iters"] * t_iter
+        cpu = {"value": 1.0 / t_solve, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": (f"FP64 banded-Cholesky SCS oracle on the same problem: factorisation "
+                          f"{t_factor:.1f} s + embedding setup {res.setup_s:.1f} s + {res.iters} ADMM "
+                          f"iterations ({t_iter:.2f} s each) timed, extrapolated to the GPU's "
+                          f"{last['iters']} iterations -> {t_solve:.0f} s per solve")}
+        log("cpu", cpu)
+    out = base_record(args, args.steps / elapsed, "solves/s", elapsed,
+                      "f32" if prec == P.FP32 else "f64",
+                      {"workload": cfg["name"], "n": n, "kernel_taps": k, "sigma": cfg["sigma"],
+                       "eps": cfg["eps"], "variables": n + 1, "constraints": 2 * n + k,
+                       "scalars": "f64"})
+    out.update({
+        "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
+        "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed,
+        "status": last["status_name"], "max_iters_cap": args.max_iters,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "k_conv<float> (direct convolution A and its adjoint A^T)",
+                     "flop_per_launch": {"A": flop_fwd, "AT": flop_adj},
+                     "launch_us": {"A": t_fwd * 1e3, "AT": t_adj * 1e3}},
+        "cpu_baseline": cpu, "verify": verify,
+    })
+    return out
+
+
+# ---------------------------------------------------------------- dense lasso (single)
+def run_lasso(args, cfg):
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1609_03488_amd as P
+
+    data = w.make_lasso(cfg)
+    m, n = cfg["m"], cfg["n"]
+    pr = P.lasso_problem(data["A"], data["b"], data["lam"])
+    stream = torch.cuda.Stream()
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10)
+    if args.max_iters:
+        st.max_iters = args.max_iters
+    s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
+    s.set_data(0, pr.b, pr.c)
+    infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
+    last = infos[-1][0]
+    t_a, t_at = s.kernel_time(2, 20), s.kernel_time(3, 20)
+    bytes_a = 4.0 * m * n
+    achieved = 2 * bytes_a / ((t_a + t_at) * 1e-3) / 1e9
+    log(f"gemv A {t_a * 1e3:.1f} us, A^T {t_at * 1e3:.1f} us, {achieved:.0f} GB/s")
+    verify = None
+    import oracle
+    prog = oracle.lasso_program(data["A"], data["b"], data["lam"])
+    if not args.no_verify:
+        x, y, sl = s.solution(0)
+        rp, rd, gap, _, _ = oracle.scs.residuals(prog, x, y, 1.0, sl)
+        f = oracle.lasso_objective(data["A"], data["b"], data["lam"], x[:n])
+        pol = oracle.polish_lasso(data["A"], data["b"], data["lam"], x[:n])
+        verify = {"res_pri_fp64": rp, "res_dual_fp64": rd, "gap_fp64": gap, "objective": f,
+                  "exact_objective": pol["obj"] if pol["kkt_ok"] else None,
+                  "rel_obj_err_vs_exact": abs(f - pol["obj"]) / abs(pol["obj"]) if pol["kkt_ok"] else None}
+        log("verify", verify)
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        res = oracle.scs_solve(prog, eps=cfg["eps"], check_every=10)
+        t = time.perf_counter() - t0
+        cpu = {"value": 1.0 / t, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": f"complete FP64 oracle solve (dense Cholesky of 3I+4A^T A, {res.iters} ADMM "
+                         f"iterations, status {res.status}) in {t:.1f} s"}
+        log("cpu", cpu)
+    out = base_record(args, args.steps / elapsed, "solves/s", elapsed, "f32",
+                      {"workload": cfg["name"], "m": m, "n": n, "eps": cfg["eps"],
+                       "variables": 2 * n + 1, "constraints": 2 * n + m + 2, "scalars": "f64"})
+    out.update({
+        "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
+        "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed, "status": last["status_name"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_gemv<float> (A and A^T, FP32, 200 MB each; fits the 256 MB MALL)",
+                     "bytes_per_launch": bytes_a, "launch_us": {"A": t_a * 1e3, "AT": t_at * 1e3}},
+        "cpu_baseline": cpu, "verify": verify,
+    })
+    return out
+
+
+# ---------------------------------------------------------------- batched lasso (BF16 MFMA)
+def run_lasso_batch(args, cfg):
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1609_03488_amd as P
+
+    data = w.make_lasso_batch(cfg)
+    m, n, B = cfg["m"], cfg["n"], cfg["batch"]
+    prs = [P.lasso_problem(data["A"], data["b"][i], data["lam"][i]) for i in range(B)]
+    stream = torch.cuda.Stream()
+    st = P.Settings.make(precision=P.BF16, eps=cfg["eps"], check_every=10)
+    s = P.Solver(prs[0].op, prs[0].l, prs[0].q, st, batch=B, stream=stream)
+    for i, pr in enumerate(prs):
+        s.set_data(i, pr.b, pr.c)
+    infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
+    last = infos[-1]
+    solves = B * args.steps
+    verify = None
+    import oracle
+    if not args.no_verify:
+        worst = 0.0
+        statuses = [inf["status_name"] for inf in last]
+        for i in range(0, B, max(1, B // 8)):
+            prog = oracle.lasso_program(data["A"], data["b"][i], data["lam"][i])
+            x, y, sl = s.solution(i)
+            rp, rd, gap, _, _ = oracle.scs.residuals(prog, x, y, 1.0, sl)
+            worst = max(worst, rp, rd, gap)
+        verify = {"worst_kkt_fp64_sampled": worst, "statuses": sorted(set(statuses))}
+        log("verify", verify)
+    # plain one-at-a-time FP32 solver on the same instances (sample)
+    nplain = min(B, args.plain_sample)
+    st32 = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10)
+    s1 = P.Solver(prs[0].op, prs[0].l, prs[0].q, st32, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nplain):
+        s1.set_data(0, prs[i].b, prs[i].c)
+        s1.solve()
+    torch.cuda.synchronize()
+    plain = nplain / (time.perf_counter() - t0)
+    log(f"plain FP32 one-at-a-time: {plain:.2f} solves/s (includes each instance's b/c upload)")
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        prog = oracle.lasso_program(data["A"], data["b"][0], data["lam"][0])
+        fac = prog.factor()
+        tf = time.perf_counter() - t0
+        nsamp = min(B, args.cpu_solves)
+        t1 = time.perf_counter()
+        for i in range(nsamp):
+            p_i = oracle.lasso_program(data["A"], data["b"][i], data["lam"][i])
+            oracle.scs_solve(p_i, eps=cfg["eps"], check_every=10, fac=fac)
+        ts = (time.perf_counter() - t1) / nsamp
+        cpu = {"value": B / (tf + B * ts), "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": f"one shared factorisation ({tf:.1f} s) + {nsamp} of {B} sequential FP64 oracle "
+                         f"solves ({ts:.2f} s each), extrapolated to {B}"}
+        log("cpu", cpu)
+    gem = s.kernel_time(2, 10), s.kernel_time(3, 10)
+    out = base_record(args, solves / elapsed, "solves/s", elapsed, "bf16",
+                      {"workload": cfg["name"], "m": m, "n": n, "batch": B, "eps": cfg["eps"],
+                       "products": "bf16 MFMA, fp32 accumulation; refinement phase bf16 hi/lo",
+                       "scalars": "f64"})
+    out.update({
+        "time_per_batch_s": elapsed / args.steps,
+        "admm_iters_max": max(i["iters"] for i in last),
+        "plain_fp32_one_at_a_time_solves_per_s": plain,
+        "speedup_vs_plain": (solves / elapsed) / plain if plain > 0 else None,
+        "dense_apply_us": {"A": gem[0] * 1e3, "AT": gem[1] * 1e3},
+        "roofline": {"bound": "hbm", "achieved": (2 * m * n * 2 * 2) / ((gem[0] + gem[1]) * 1e-3) / 1e9,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": (2 * m * n * 2 * 2) / ((gem[0] + gem[1]) * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "traffic": None,
+                     "kernel": "pack + k_gemm_bf16 + reduce (A and A^T as BF16 MFMA GEMMs over the batch)",
+                     "bytes_per_launch": 2 * m * n * 2},
+        "cpu_baseline": cpu, "verify": verify,
+    })
+    return out
+
+
+# ---------------------------------------------------------------- serving replay
+def run_serve(args, cfg):
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1609_03488_amd as P
+    from paper_1609_03488_amd.serve import replay
+
+    trace = w.serving_trace(cfg["count"], cfg["rate"], cfg["seed"])
+    if args.serve_count:
+        trace = trace[:args.serve_count]
+    log(f"generating {len(trace)} requests")
+    probs = {}
+    for r in trace:
+        d = w.serving_request_data(r, cfg["density"], cfg["noise_var"])
+        probs[r.rid] = (d, P.deconv_problem(d["c"], d["b"]))
+    # every request runs whole steps in one workgroup (fused path); the CG loop
+    # length is data dependent inside the kernel
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10,
+                         cg_max_iters=args.serve_cg, fused_max=args.serve_fused_max)
+    stream = torch.cuda.Stream()
+    res = replay(trace, lambda r: probs[r.rid][1], settings=st, workspace_bytes=args.serve_ws << 30,
+                 steps_per_call=10, stream=stream, log=log, keep_x=not args.no_verify)
+    log(f"served {res['completed']} in {res['wall_s']:.1f}s: {res['solves_per_s']:.1f} solves/s, "
+        f"p50 {res['p50_s']:.2f}s p99 {res['p99_s']:.2f}s")
+    verify = None
+    if not args.no_verify:
+        import oracle
+        worst = 0.0
+        for c in res["completions"][:: max(1, len(res["completions"]) // 20)]:
+            d = probs[c.rid][0]
+            f = oracle.deconv_objective(d["c"], d["b"], c.x)
+            noise = float(np.linalg.norm(d["b"] - np.convolve(d["c"], d["x_true"])))
+            worst = max(worst, f / noise)
+        verify = {"max_objective_over_noise_norm_sampled": worst, "solved": res["solved"]}
+        log("verify", verify)
+    # plain one-at-a-time FIFO on a prefix of the trace
+    nfifo = min(len(trace), args.plain_sample)
+    fifo = replay(trace[:nfifo], lambda r: probs[r.rid][1], settings=st,
+                  workspace_bytes=2 << 30, max_slots=1, steps_per_call=10, stream=stream)
+    log(f"FIFO one-at-a-time on {nfifo}: {fifo['solves_per_s']:.2f} solves/s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        samp = [r for r in trace if r.n <= 5000][: args.cpu_solves]
+        tot = 0.0
+        for r in samp:
+            d = probs[r.rid][0]
+            t0 = time.perf_counter()
+            oracle.scs_solve(oracle.deconv_program(d["c"], d["b"]), eps=cfg["eps"], check_every=10)
+            tot += time.perf_counter() - t0
+        cpu = {"value": len(samp) / tot, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": f"{len(samp)} complete FP64 oracle solves of the trace's requests with n <= 5000 "
+                         f"(smaller than the trace average, so this over-states the oracle) in {tot:.1f} s"}
+        log("cpu", cpu)
+    out = base_record(args, res["solves_per_s"], "solves/s", res["wall_s"], "f32",
+                      {"workload": cfg["name"], "requests": len(trace), "rate_per_s": cfg["rate"],
+                       "eps": cfg["eps"], "scalars": "f64"})
+    out.update({
+        "p50_latency_s": res["p50_s"], "p99_latency_s": res["p99_s"], "completed": res["completed"],
+        "solved": res["solved"], "mean_admm_iters": res["mean_iters"],
+        "plain_fifo_solves_per_s": fifo["solves_per_s"],
+        "plain_fifo_sample": nfifo, "cpu_baseline": cpu, "verify": verify,
+    })
+    return out
 
 
 def main():
@@ -69,114 +359,50 @@ def main():
     ap.add_argument("--workload", default="deconv_n1M_k1025")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-solves", type=int, default=4)
+    ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--max-iters", type=int, default=None,
+                    help="cap on ADMM iterations (profiling runs; the JSON then says so)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied by a plain device copy after the run (counter calibration)")
+    ap.add_argument("--serve-count", type=int, default=None)
+    ap.add_argument("--serve-ws", type=int, default=16, help="server workspace, GiB")
+    ap.add_argument("--serve-cg", type=int, default=10, help="CG iterations per step, upper bound")
+    ap.add_argument("--serve-fused-max", type=int, default=1 << 20,
+                    help="largest n + m served by the fused one-workgroup-per-request path")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}, WORLD_SIZE={world}); "
               "this build has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
     import torch
     import workloads as w
-    import paper_1609_03488_amd as P
-
-    cfg = w.workload(args.workload)
-    if cfg["family"] != "deconv":
-        raise SystemExit("bench.py times the deconvolution workloads")
-    log("generating", cfg["name"])
-    data = w.make_deconv(cfg)
-    n, k = cfg["n"], cfg["k"]
-    pr = P.deconv_problem(data["c"], data["b"])
     torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()
-    prec = P.FP64 if cfg["precision"] == "fp64" else P.FP32
-    st = P.Settings.make(precision=prec, eps=cfg["eps"], check_every=10)
-    s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
-    s.set_data(0, pr.b, pr.c)
-    log(f"workspace {s.workspace_bytes / 2**20:.1f} MiB; warmup {args.warmup}")
-    for i in range(args.warmup):
-        s.reset()
-        info = s.solve()[0]
-        log(f"warmup {i}: {info['status_name']} iters={info['iters']} cg={info['cg_iters']} "
-            f"t={info['setup_s'] + info['solve_s']:.3f}s")
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        s.reset()
-        infos.append(s.solve()[0])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for i, info in enumerate(infos):
-        log(f"step {i}: {info['status_name']} iters={info['iters']} cg={info['cg_iters']} "
-            f"res=({info['res_pri']:.2e},{info['res_dual']:.2e},{info['gap']:.2e})")
-    ms_per_step = 1000.0 * elapsed / args.steps
-    last = infos[-1]
-    cg_total = sum(i["cg_iters"] for i in infos)
-
-    # dominant kernel: the direct convolution (A) and its adjoint (A^T)
-    t_fwd = s.kernel_time(0, 20)
-    t_adj = s.kernel_time(1, 20)
-    flop_fwd = 2.0 * k * (n + k - 1)
-    flop_adj = 2.0 * k * n
-    achieved = (flop_fwd + flop_adj) / ((t_fwd + t_adj) * 1e-3) / 1e12
-    log(f"conv fwd {t_fwd * 1e3:.1f} us, adj {t_adj * 1e3:.1f} us, {achieved:.1f} TFLOP/s")
-
-    verify = None
-    if not args.no_verify:
-        import oracle
-        x, y, sl = s.solution(0)
-        prog = oracle.deconv_program(data["c"], data["b"])
-        rp, rd, gap, _, _ = oracle.scs.residuals(prog, x, y, 1.0, sl)
-        f = oracle.deconv_objective(data["c"], data["b"], x[:n])
-        noise = float(np.linalg.norm(data["b"] - np.convolve(data["c"], data["x_true"])))
-        verify = {"res_pri_fp64": rp, "res_dual_fp64": rd, "gap_fp64": gap, "objective": f,
-                  "objective_bound_noise_norm": noise}
-        log("verify", verify)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(cfg, data, int(last["iters"]), args.cpu_iters)
-        log("cpu", cpu)
-
-    out = {
-        "metric": METRIC,
-        "value": args.steps / elapsed,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32" if prec == P.FP32 else "f64",
-        "data": "synthetic",
-        "config": {"workload": cfg["name"], "n": n, "kernel_taps": k, "sigma": cfg["sigma"],
-                   "eps": cfg["eps"], "variables": n + 1, "constraints": 2 * n + k,
-                   "scalars": "f64"},
-        "time_to_eps_s": ms_per_step / 1000.0,
-        "admm_iters": last["iters"],
-        "cg_iters": last["cg_iters"],
-        "cg_matvecs_per_s": cg_total / elapsed,
-        "status": last["status_name"],
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP32_VECTOR_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-            "traffic": None,
-            "kernel": "k_conv<float> (direct convolution A and its adjoint A^T)",
-            "flop_per_launch": {"A": flop_fwd, "AT": flop_adj},
-            "launch_us": {"A": t_fwd * 1e3, "AT": t_adj * 1e3},
-        },
-        "cpu_baseline": cpu,
-        "verify": verify,
-    }
+    cfg = w.workload(args.workload)
+    log("workload", cfg["name"])
+    fam = cfg["family"]
+    if fam == "deconv":
+        out = run_deconv(args, cfg)
+    elif fam == "lasso":
+        out = run_lasso(args, cfg)
+    elif fam == "lasso_batch":
+        out = run_lasso_batch(args, cfg)
+    elif fam == "serve":
+        out = run_serve(args, cfg)
+    else:
+        raise SystemExit(f"unknown workload family {fam}")
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale
+        # the counters of the solver's kernels to bytes
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nb
     print(json.dumps(out), flush=True)
 
 

@@ -97,8 +97,21 @@ typedef struct {
     double setup_tol;      /* relative CG tolerance of the embedding-vector solve     */
     int32_t setup_max_iters; /* CG iteration limit of that solve                      */
     int32_t use_graph;     /* 1: replay each block of check_every steps as a hipGraph */
-    int32_t bf16_final_iters; /* CGS_BF16: FP32-operator steps after the BF16 phase   */
-    int32_t reserved[7];
+    int32_t bf16_phase1_digits; /* CGS_BF16: the BF16-product phase solves to
+                              max(eps, 10^-digits); the refinement phase (BF16 hi/lo
+                              products, ~16 significant bits) then continues from its
+                              state to eps with a fresh setup solve (default 3)       */
+    int32_t cg_adaptive;   /* 1: CG launches per step follow the most CG iterations any
+                              instance used in a step of the previous check interval
+                              (+2, capped at cg_max_iters); 0: always cg_max_iters.
+                              A server always uses 0 (results independent of the mix) */
+    int32_t fused_max;     /* instances with n + m <= fused_max run whole ADMM steps in
+                              one workgroup each (one launch per check interval, CG
+                              loop inside the kernel); applies when every instance of
+                              the solver / server qualifies; 0 disables (default 65536) */
+    int32_t conv_mfma;     /* 1: FP32 convolutions run on the matrix cores (16x16x4 FP32
+                              MFMA over Toeplitz blocks of the taps); 0: vector ALU  */
+    int32_t reserved[4];
 } cgs_settings;
 
 /* Per-instance result. */
@@ -175,7 +188,9 @@ int cgs_solver_set_data(cgs_solver* s, int64_t inst, const double* b, const doub
  * method again, setup included, without any host-to-device transfer. */
 int cgs_solver_reset(cgs_solver* s, int64_t inst);
 /* Solve every instance from its current state (fresh: u = v = (0, 0, 1)).
- * info: array of `batch` entries (may be NULL). */
+ * info: array of `batch` entries (may be NULL).  With CGS_BF16 and dense
+ * blocks, the dense applies of all instances run as one BF16 MFMA GEMM
+ * (FP32 accumulation); the solve has two phases (see bf16_phase1_digits). */
 int cgs_solve(cgs_solver* s, cgs_info* info);
 /* Run exactly `iters` ADMM steps on every unfinished instance, with no
  * termination test (the setup solve runs first if needed). */
@@ -205,7 +220,8 @@ int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, 
 /* Device time of one operator kernel class, measured with HIP events on the
  * solver's stream around `reps` back-to-back launches on the current iterate
  * vectors: kernel 0 = convolution (A), 1 = convolution adjoint (A^T),
- * 2 = dense block (A), 3 = dense block (A^T), 4 = the whole normal-operator
+ * 2 = dense block (A), 3 = dense block (A^T) (for a CGS_BF16 batch: the
+ * pack + MFMA GEMM + reduce of all instances), 4 = the whole normal-operator
  * application p + A^T A p.  *avg_ms receives the mean time per launch (per
  * operator block, for 0-3); CGS_ENOTFOUND if the operator has no such block. */
 int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* avg_ms);

@@ -30,7 +30,8 @@ class Settings(C.Structure):
         ("check_every", C.c_int32), ("precision", C.c_int32), ("cg_max_iters", C.c_int32),
         ("cg_tol", C.c_double), ("cg_rate", C.c_double), ("cg_floor", C.c_double),
         ("setup_tol", C.c_double), ("setup_max_iters", C.c_int32), ("use_graph", C.c_int32),
-        ("bf16_final_iters", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("bf16_phase1_digits", C.c_int32), ("cg_adaptive", C.c_int32),
+        ("fused_max", C.c_int32), ("conv_mfma", C.c_int32), ("reserved", C.c_int32 * 4),
     ]
 
     @classmethod

@@ -38,6 +38,7 @@ int check_block(const cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int6
 // Device bytes of the solver: tables, reduction scratch, staging, operator data, regions.
 struct SolverLayout {
     size_t tab = 0, work = 0, stg = 0, opb = 0, region = 0, total = 0;
+    size_t panel = 0, part = 0;          // BF16 GEMM panel (hi and lo) and split-K partials
     int64_t stg_doubles = 0;
 };
 
@@ -65,7 +66,17 @@ int solver_layout(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, con
     L->stg = cgs::align256((size_t)L->stg_doubles * sizeof(double));
     L->opb = cgs::align256(cgs::op_dev_bytes(*op, st->precision));
     L->region = cgs::region_bytes(op->n, op->m, st->precision);
-    L->total = L->tab + L->work + L->stg + L->opb + (size_t)batch * L->region;
+    if (st->precision == CGS_BF16) {
+        for (const cgs::DenseBlock& db : shape.dense) {
+            for (int adj = 0; adj < 2; ++adj) {
+                const int64_t N = adj ? db.cols : db.rows, kpad = adj ? db.ldt : db.ld;
+                const cgs::GemmPlan g = cgs::gemm_plan(N, kpad, (int)batch);
+                L->panel = std::max(L->panel, cgs::align256((size_t)g.mpad * kpad * 2));
+                L->part = std::max(L->part, cgs::align256(cgs::gemm_part_bytes(g)));
+            }
+        }
+    }
+    L->total = L->tab + L->work + L->stg + L->opb + 2 * L->panel + L->part + (size_t)batch * L->region;
     return CGS_OK;
 }
 
@@ -206,7 +217,10 @@ void cgs_settings_default(cgs_settings* st) {
     st->setup_tol = 1e-7;
     st->setup_max_iters = 500;
     st->use_graph = 1;
-    st->bf16_final_iters = 50;
+    st->bf16_phase1_digits = 3;
+    st->cg_adaptive = 1;
+    st->fused_max = 65536;
+    st->conv_mfma = 1;
 }
 
 // ---------------------------------------------------------------- solver
@@ -243,6 +257,12 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
     CGS_TRY(e.init_host_buffers(L.tab, (int)batch, L.stg_doubles));
     e.stg.dev = (double*)p; p += L.stg;
     char* opdata = p; p += L.opb;
+    if (st->precision == CGS_BF16 && L.part > 0) {
+        e.use_gemm = 1;
+        e.panel_hi = (uint16_t*)p; p += L.panel;
+        e.panel_lo = (uint16_t*)p; p += L.panel;
+        e.gemm_part = (float*)p; p += L.part;
+    }
     CGS_TRY(cgs::op_upload(*op, st->precision, opdata, e.stg, e.stream, &s->opdev));
     std::vector<cgs::InstRec> recs((size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
@@ -309,13 +329,21 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
         if (kernel <= 1) {
             // A u_x into the scratch Y vector, A^T u_y into the scratch X vector
             for (const auto& c : cl)
-                cgs::launch_conv(e.prec, e.T, c, kernel, kernel ? cgs::XT : cgs::YT,
-                                 kernel ? cgs::YU : cgs::XU, 1.0, cgs::G_ALL, e.stream), ++launches;
+                e.conv(c, kernel, kernel ? cgs::XT : cgs::YT, kernel ? cgs::YU : cgs::XU, 1.0, cgs::G_ALL),
+                    ++launches;
         } else if (kernel <= 3) {
             const int adj = kernel == 3;
-            for (const auto& d : dl)
-                cgs::launch_gemv(e.prec, e.T, d, adj, adj ? cgs::XT : cgs::YT, adj ? cgs::YU : cgs::XU,
-                                 1.0, cgs::G_ALL, e.stream), ++launches;
+            if (e.use_gemm) {
+                // the batch's dense applies: pack + BF16 MFMA GEMM + reduce
+                for (const cgs::DenseBlock& db : s->opdev.dense)
+                    cgs::launch_gemm_apply(e.inst_dev, e.T.ninst, db, adj, adj ? cgs::XT : cgs::YT,
+                                           adj ? cgs::YU : cgs::XU, 1.0, cgs::G_ALL, e.gemm_corr,
+                                           e.panel_hi, e.panel_lo, e.gemm_part, e.stream), ++launches;
+            } else {
+                for (const auto& d : dl)
+                    cgs::launch_gemv(e.prec, e.T, d, adj, adj ? cgs::XT : cgs::YT, adj ? cgs::YU : cgs::XU,
+                                     1.0, cgs::G_ALL, e.stream), ++launches;
+            }
         } else {
             e.apply(0, cgs::YT, cgs::XP, -1, 1.0, cgs::G_ALL);
             e.apply(1, cgs::XT, cgs::YT, cgs::XP, 1.0, cgs::G_ALL);
@@ -352,13 +380,65 @@ static int run_setup_if_needed(cgs_solver* s, bool* did) {
     return CGS_OK;
 }
 
+static int solve_rounds(cgs_solver* s);
+
 int cgs_solve(cgs_solver* s, cgs_info* info) {
     if (!s) return fail(CGS_EINVAL, "solver is null");
     CGS_TRY(ensure_data(s));
     cgs::Engine& e = s->eng;
     const double t0 = now_s();
-    CGS_TRY(run_setup_if_needed(s, nullptr));
-    const double t1 = now_s();
+    double t1 = t0;
+    if (e.use_gemm) {
+        // Phase 1: BF16 products, to max(eps, 10^-digits).  Phase 2: the
+        // refinement operator (hi/lo products) from phase 1's state, with the
+        // embedding vector recomputed for that operator, to eps.
+        const double eps = e.st.eps;
+        const double eps1 = std::max(eps, std::pow(10.0, -(double)e.st.bf16_phase1_digits));
+        e.gemm_corr = 0;
+        e.st.eps = eps1;
+        e.drop_graph();
+        CGS_TRY(run_setup_if_needed(s, nullptr));
+        e.refresh();
+        t1 = now_s();
+        int rc = solve_rounds(s);
+        e.st.eps = eps;
+        if (rc != CGS_OK) return rc;
+        if (eps1 > eps) {
+            CGS_TRY(e.fetch_scalars());
+            for (int i = 0; i < e.T.ninst; ++i) {
+                const double* sc = e.scalars(i);
+                if (sc[cgs::SC_STATUS] == (double)CGS_SOLVED) {
+                    CGS_TRY(e.set_scalar(i, cgs::SC_STATUS, 0.0));
+                    CGS_TRY(e.set_scalar(i, cgs::SC_ACTIVE, 1.0));
+                    CGS_TRY(e.set_scalar(i, cgs::SC_PHASE, 0.0));
+                }
+            }
+            e.gemm_corr = 1;
+            e.drop_graph();
+            CGS_TRY(run_setup_if_needed(s, nullptr));
+            e.refresh();
+            CGS_TRY(solve_rounds(s));
+        }
+    } else {
+        CGS_TRY(run_setup_if_needed(s, nullptr));
+        e.refresh();   // carried A z, (I + A^T A) z of the warm start
+        t1 = now_s();
+        CGS_TRY(solve_rounds(s));
+    }
+    const double t2 = now_s();
+    if (info) {
+        for (int i = 0; i < e.T.ninst; ++i) {
+            e.fill_info(i, &info[i]);
+            info[i].setup_s = t1 - t0;
+            info[i].solve_s = t2 - t1;
+        }
+    }
+    return CGS_OK;
+}
+
+// ADMM rounds (check_every steps + termination test) until no instance runs.
+static int solve_rounds(cgs_solver* s) {
+    cgs::Engine& e = s->eng;
     for (;;) {
         CGS_TRY(e.fetch_scalars());
         bool any = false;
@@ -373,15 +453,8 @@ int cgs_solve(cgs_solver* s, cgs_info* info) {
         if (!any) break;
         const int64_t rem = (int64_t)e.st.max_iters - (int64_t)min_it;
         const int nsteps = (int)std::max<int64_t>(1, std::min<int64_t>(e.st.check_every, rem));
+        e.adapt_cg();
         CGS_TRY(e.round(nsteps));
-    }
-    const double t2 = now_s();
-    if (info) {
-        for (int i = 0; i < e.T.ninst; ++i) {
-            e.fill_info(i, &info[i]);
-            info[i].setup_s = t1 - t0;
-            info[i].solve_s = t2 - t1;
-        }
     }
     return CGS_OK;
 }
@@ -392,7 +465,11 @@ int cgs_solver_iterate(cgs_solver* s, int32_t iters) {
     CGS_TRY(ensure_data(s));
     cgs::Engine& e = s->eng;
     CGS_TRY(run_setup_if_needed(s, nullptr));
-    for (int i = 0; i < iters; ++i) e.admm_step();
+    e.cg_launch = e.st.cg_max_iters;
+    e.refresh();
+    if (e.use_fused) e.fused_steps(iters, 0);
+    else
+        for (int i = 0; i < iters; ++i) e.admm_step();
     CGS_HIP(hipGetLastError());
     CGS_HIP(hipStreamSynchronize(e.stream));
     return CGS_OK;
@@ -508,7 +585,7 @@ int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, 
     int done = 0;
     while (done < max_iters) {
         const int nb = std::min(8, max_iters - done);
-        for (int j = 0; j < nb; ++j) e.cg_iter(cgs::XZ, cgs::G_ANY_CG, max_iters);
+        for (int j = 0; j < nb; ++j) e.cg_iter(cgs::XZ, cgs::G_ANY_CG, max_iters, 0);
         done += nb;
         CGS_TRY(e.fetch_scalars());
         if (e.scalars(0)[cgs::SC_CGACT] == 0.0) break;
@@ -549,6 +626,7 @@ int cgs_server_create(int64_t max_slots, const cgs_settings* st, void* workspace
     e.prec = cgs::work_prec(st->precision);
     e.st = *st;
     e.stream = (hipStream_t)stream;
+    e.st.cg_adaptive = 0;     // results must not depend on the other requests in the mix
     e.cg_launch = st->cg_max_iters;
     // tables and reduction scratch: a fixed slice of the workspace
     const size_t tab = cgs::align256(std::max<size_t>(size_t(1) << 20, ws_bytes / 64));
@@ -706,6 +784,7 @@ int cgs_server_step(cgs_server* sv, int32_t steps, int64_t* n_running) {
             if (sc[cgs::SC_ACTIVE] != 0.0 && sc[cgs::SC_PHASE] == 0.0) need_setup = true;
         }
         if (need_setup) CGS_TRY(e.setup());
+        e.refresh();
         const int rounds = (steps + e.st.check_every - 1) / e.st.check_every;
         for (int r = 0; r < rounds; ++r) {
             CGS_TRY(e.round(e.st.check_every));

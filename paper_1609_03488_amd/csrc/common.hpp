@@ -27,6 +27,7 @@ enum XVec : int {
     XQ,       // (I + A^T A) p
     XH,       // CG right-hand side
     XT,       // scratch (A^T y for residuals / diagnostics)
+    XK,       // (I + A^T A) z, carried through the CG updates
     NXV
 };
 // Y-space vectors (length m)
@@ -38,6 +39,7 @@ enum YVec : int {
     YW,       // w_y = u_y + v_s
     YZ,       // z_y = w_y + A z_x
     YT,       // scratch (A p, A u_x)
+    YA,       // A z, carried through the CG updates
     NYV
 };
 
@@ -59,6 +61,8 @@ enum Scal : int {
     SC_STATUS,                                 // CGS_* outcome
     SC_SETUPIT,                                // CG iterations of the setup solve
     SC_CUX, SC_BUY,                            // raw c^T u_x, b^T u_y at the last check
+    SC_CGMAX,                                  // most CG iterations of a step since the last check
+    SC_CGMAXLAST,                              // ... over the previous check interval
     NSC_USED
 };
 constexpr int NSC = 32;      // doubles reserved per instance (256 bytes)
@@ -87,6 +91,8 @@ struct InstDesc {
     int32_t yt0, yt1;    // Y-tile range
     int32_t sg0, sg1;    // SOC segment range
     int32_t id0, id1;    // identity-block range
+    int32_t cb0, cb1;    // convolution-block range (Tables::cblk)
+    int32_t db0, db1;    // dense-block range (Tables::dblk)
 };
 
 // A tile of an X or Y vector: `len` elements from instance-local `start`.
@@ -131,8 +137,10 @@ struct DenseBlock {      // rows x cols block
     int64_t ld, ldt;     // leading dimensions of a (rows x ld) and at (cols x ldt)
     const void* a;       // working precision, row-major
     const void* at;      // its transpose, row-major
-    const void* a16;     // BF16 copies (CGS_BF16 only) or null
+    const void* a16;     // BF16 (round to nearest even) copies, CGS_BF16 only, or null
     const void* at16;
+    const void* a16lo;   // BF16 rounding of the remainder a - a16 (refinement products)
+    const void* at16lo;
     double scale;
 };
 
@@ -152,15 +160,19 @@ struct Tables {
     double* seg_val;     // 2 per segment: head value, tail sum of squares
     int* seg_cnt;        // 1 per segment
     const IdBlock* ids;
+    const struct ConvBlock* cblk;
+    const struct DenseBlock* dblk;
     double* xpart;       // 4 per X tile
     double* ypart;       // 4 per Y tile
     int nx_tiles, ny_tiles, nseg, ninst;
 };
 
-constexpr int VEC_TILE = 1024;     // elements per X/Y tile
+constexpr int VEC_TILE = 2048;     // elements per X/Y tile
 constexpr int VEC_NT = 256;        // threads per vector-kernel block
-constexpr int CONV_TILE_F32 = 2048;  // outputs per convolution tile (256 threads x 8)
-constexpr int CONV_TILE_F64 = 1024;  // (256 threads x 4)
+constexpr int CONV_TILE_F32 = 512;   // outputs per convolution tile (64 lanes x 8)
+constexpr int CONV_TILE_F64 = 256;   // (64 lanes x 4)
+constexpr int CONV_KC_MAX_F32 = 2048;  // taps staged per pass (LDS: (512 + 2*2048 + 16) * 4 B)
+constexpr int CONV_KC_MAX_F64 = 1024;
 constexpr int CONV_R_F32 = 8;        // taps are padded to a multiple of this
 constexpr int CONV_R_F64 = 4;
 constexpr int DENSE_ROWS = 4;        // rows per dense-GEMV tile

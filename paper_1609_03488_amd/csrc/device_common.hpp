@@ -1,0 +1,255 @@
+// Device helpers shared by the HIP sources of the engine.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace cgs {
+
+#define DEVI __device__ __forceinline__
+
+// Pointers into instance regions and operator data are loaded from tables, so
+// the compiler cannot infer their address space; they are declared global
+// (address space 1) to get global (not flat) memory instructions.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+
+// ---------------------------------------------------------------- helpers
+template <typename T>
+DEVI gptr<T> xvec(const InstDesc& d, int k) {
+    return (gptr<T>)(d.base + REGION_HDR) + (int64_t)k * d.nxs;
+}
+template <typename T>
+DEVI gptr<T> yvec(const InstDesc& d, int k) {
+    return (gptr<T>)(d.base + REGION_HDR) + (int64_t)NXV * d.nxs + (int64_t)k * d.nys;
+}
+DEVI gptr<double> scal(const InstDesc& d) { return (gptr<double>)d.base; }
+DEVI int* counters(const InstDesc& d) { return reinterpret_cast<int*>(d.base + NSC * 8); }
+
+DEVI bool gate_ok(gptr<const double> sc, int gate) {
+    switch (gate) {
+        case G_ALL: return true;
+        case G_SETUP: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0;
+        case G_SETUP_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0 && sc[SC_CGACT] != 0.0;
+        case G_ADMM:
+        case G_CHECK: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0;
+        case G_ADMM_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0 && sc[SC_CGACT] != 0.0;
+        case G_ANY_CG: return sc[SC_CGACT] != 0.0;
+        default: return false;
+    }
+}
+
+DEVI double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over the workgroup in a fixed order; the result is valid in thread 0.
+template <int NT>
+DEVI double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) r += sh[i];
+    }
+    return r;
+}
+
+// Fixed-order sum of partial slot j over tiles [t0, t1) (partials of the
+// previous kernel: the kernel boundary makes them visible).
+template <int NT>
+DEVI double sum_parts(const double* part, int t0, int t1, int j, double* sh) {
+    double s = 0.0;
+    for (int i = t0 + (int)threadIdx.x; i < t1; i += NT) s += part[4 * (int64_t)i + j];
+    return block_sum<NT>(s, sh);
+}
+
+// Tile of a kernel that walks the X tiles and then the Y tiles.
+struct XYTile {
+    VecTile t;
+    bool is_y;
+    int index;   // index in its own table
+};
+DEVI XYTile xy_tile(const Tables& tb) {
+    XYTile r;
+    const int b = blockIdx.x;
+    if (b < tb.nx_tiles) {
+        r.t = tb.xt[b];
+        r.is_y = false;
+        r.index = b;
+    } else {
+        r.t = tb.yt[b - tb.nx_tiles];
+        r.is_y = true;
+        r.index = b - tb.nx_tiles;
+    }
+    return r;
+}
+
+// 16-byte vector access helpers (native clang vector types)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = f32x4; static constexpr int W = 4; };
+template <> struct Vec16<double> { using type = f64x2; static constexpr int W = 2; };
+
+template <typename T>
+DEVI void vec_get(const typename Vec16<T>::type& v, T* o) {
+#pragma unroll
+    for (int e = 0; e < Vec16<T>::W; ++e) o[e] = v[e];
+}
+
+// ---------------------------------------------------------------- operator: convolution
+// Direct full convolution and its adjoint (valid correlation) in one
+// correlation form:  out[o] += s * sum_t w[t] * in[o + off + t]  with
+//   A x : w = reversed taps, off = -(k-1), in = x (zero outside [0, n_in));
+//   A^T y: w = taps,          off = 0,      in = y.
+// One wave computes a tile of CONV_NT * R consecutive outputs; each lane keeps
+// R outputs in registers and slides a 2R-wide register window over an LDS copy
+// of the tile's input window (TILE + kc - 1 values, staged with batched
+// loads); the taps of the chunk sit in LDS and are read as broadcasts.  The
+// LDS size follows the kernel length (dynamic shared memory), so kernels up to
+// CONV_KC_MAX taps need a single staging pass.
+constexpr int CONV_NT = 64;
+template <typename T> struct ConvCfg;
+template <> struct ConvCfg<float> { static constexpr int R = 8; };
+template <> struct ConvCfg<double> { static constexpr int R = 4; };
+static_assert(CONV_NT * ConvCfg<float>::R == CONV_TILE_F32 && ConvCfg<float>::R == CONV_R_F32, "conv tile");
+static_assert(CONV_NT * ConvCfg<double>::R == CONV_TILE_F64 && ConvCfg<double>::R == CONV_R_F64, "conv tile");
+
+template <typename T, int R>
+DEVI void lds_vec(T (&v)[R], const T* p) {   // 16-byte aligned LDS reads
+    using V = typename Vec16<T>::type;
+    constexpr int VW = Vec16<T>::W;
+#pragma unroll
+    for (int j = 0; j < R / VW; ++j) {
+        const V q = reinterpret_cast<const V*>(p)[j];
+        vec_get<T>(q, v + j * VW);
+    }
+}
+
+template <typename T, int R>
+DEVI void conv_step(T (&acc)[R], const T (&lo)[R], const T (&hi)[R], const T (&tw)[R]) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const T xv = (r + u < R) ? lo[r + u] : hi[r + u - R];
+            acc[r] = fma(tw[u], xv, acc[r]);
+        }
+    }
+}
+
+// relaxed point minus v for a Y entry
+template <typename T>
+DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, double& ubar) {
+    const double uy = (double)yvec<T>(d, YU)[i];
+    const double ut_y = (double)yvec<T>(d, YZ)[i] - ut * (double)yvec<T>(d, YG)[i];
+    ubar = alpha * ut_y + (1.0 - alpha) * uy;
+    return ubar - (double)yvec<T>(d, YV)[i];
+}
+
+// One tile of NT * R consecutive outputs (from `ot`) of a convolution block
+// (adj = 0: A, out is Y; adj = 1: A^T, out is X), out += sigma * scale * (...).
+// smem: (NT * R + 2 * KC + 2R) elements of T.  Called by every thread of the
+// workgroup; starts and ends with a workgroup barrier.
+template <typename T, int NT>
+DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, int in, double sigma,
+                    int64_t ot, int KC, unsigned char* smem) {
+    constexpr int R = ConvCfg<T>::R, TILE = NT * R;
+    T* win = reinterpret_cast<T*>(smem);        // TILE + KC + 2R entries
+    T* taps = win + TILE + KC + 2 * R;          // KC entries
+    int64_t n_out, n_in, off;
+    gptr<const T> w;
+    gptr<T> o;
+    gptr<const T> src;
+    if (!adj) {
+        n_out = cb.n_in + cb.k - 1;
+        n_in = cb.n_in;
+        off = -(cb.k - 1);
+        w = (gptr<const T>)cb.w_fwd;
+        o = yvec<T>(d, out) + cb.row0;
+        src = xvec<T>(d, in) + cb.col0;
+    } else {
+        n_out = cb.n_in;
+        n_in = cb.n_in + cb.k - 1;
+        off = 0;
+        w = (gptr<const T>)cb.w_adj;
+        o = xvec<T>(d, out) + cb.col0;
+        src = yvec<T>(d, in) + cb.row0;
+    }
+    const int tid = threadIdx.x;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = T(0);
+
+    for (int64_t t0 = 0; t0 < cb.kpad; t0 += KC) {
+        const int kc = (int)((cb.kpad - t0) < KC ? (cb.kpad - t0) : KC);
+        __syncthreads();
+        // stage the input window with 8 independent loads in flight per lane
+        const int64_t w0 = ot + off + t0;
+        const int nwin = TILE + kc + 2 * R;
+        for (int base = 0; base < nwin; base += 8 * NT) {
+            T v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * NT + tid;
+                const int64_t g = w0 + i;
+                v[j] = (i < nwin && g >= 0 && g < n_in) ? src[g] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * NT + tid;
+                if (i < nwin) win[i] = v[j];
+            }
+        }
+        for (int base = 0; base < kc; base += 8 * NT) {
+            T v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * NT + tid;
+                v[j] = i < kc ? w[t0 + i] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = base + j * NT + tid;
+                if (i < kc) taps[i] = v[j];
+            }
+        }
+        __syncthreads();
+        const T* wp = win + tid * R;
+        T a[R], b[R], tw[R];
+        lds_vec<T, R>(a, wp);
+        int tt = 0;
+        for (; tt + 2 * R <= kc; tt += 2 * R) {
+            lds_vec<T, R>(b, wp + tt + R);
+            lds_vec<T, R>(tw, taps + tt);
+            conv_step<T, R>(acc, a, b, tw);
+            lds_vec<T, R>(a, wp + tt + 2 * R);
+            lds_vec<T, R>(tw, taps + tt + R);
+            conv_step<T, R>(acc, b, a, tw);
+        }
+        if (tt < kc) {
+            lds_vec<T, R>(b, wp + tt + R);
+            lds_vec<T, R>(tw, taps + tt);
+            conv_step<T, R>(acc, a, b, tw);
+        }
+    }
+    const double s = sigma * cb.scale;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t oi = ot + (int64_t)tid * R + r;
+        if (oi < n_out) o[oi] = (T)((double)o[oi] + s * (double)acc[r]);
+    }
+    __syncthreads();
+}
+
+
+}  // namespace cgs

@@ -49,14 +49,15 @@ int validate_settings(const cgs_settings* s) {
         return fail(CGS_EINVAL, "cg_tol, cg_rate, cg_floor must be finite and >= 0");
     if (!(s->setup_tol > 0.0) || !std::isfinite(s->setup_tol)) return fail(CGS_EINVAL, "setup_tol must be finite and > 0");
     if (s->setup_max_iters < 1) return fail(CGS_EINVAL, "setup_max_iters must be >= 1");
-    if (s->bf16_final_iters < 0) return fail(CGS_EINVAL, "bf16_final_iters must be >= 0");
+    if (s->bf16_phase1_digits < 0 || s->bf16_phase1_digits > 15)
+        return fail(CGS_EINVAL, "bf16_phase1_digits must be in [0, 15]");
     return CGS_OK;
 }
 
 // ---------------------------------------------------------------- layouts
 static int64_t conv_r(int precision) { return precision == CGS_FP64 ? CONV_R_F64 : CONV_R_F32; }
 static int64_t conv_tile(int precision) { return precision == CGS_FP64 ? CONV_TILE_F64 : CONV_TILE_F32; }
-static int64_t dense_ld(int64_t cols) { return round_up(cols, 8); }
+static int64_t dense_ld(int64_t cols) { return round_up(cols, 16); }   // K of the MFMA steps
 
 int64_t staging_doubles(const cgs_op& op, int64_t max_vec) {
     int64_t need = std::max<int64_t>(max_vec, int64_t(1) << 16);
@@ -84,7 +85,7 @@ size_t op_dev_bytes(const cgs_op& op, int precision) {
         if (b.kind == CGS_BLOCK_DENSE) {
             const size_t ld = dense_ld(b.cols), ldt = dense_ld(b.rows);
             tot += align256(b.rows * ld * sz) + align256(b.cols * ldt * sz);
-            if (precision == CGS_BF16) tot += align256(b.rows * ld * 2) + align256(b.cols * ldt * 2);
+            if (precision == CGS_BF16) tot += 2 * (align256(b.rows * ld * 2) + align256(b.cols * ldt * 2));
         }
     }
     return tot;
@@ -165,10 +166,14 @@ int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hi
             if (precision == CGS_BF16) {
                 db.a16 = p;
                 p += align256(rows * ld * 2);
+                db.a16lo = p;
+                p += align256(rows * ld * 2);
                 db.at16 = p;
                 p += align256(cols * ldt * 2);
-                launch_to_bf16((const float*)db.a, (uint16_t*)db.a16, rows * ld, st);
-                launch_to_bf16((const float*)db.at, (uint16_t*)db.at16, cols * ldt, st);
+                db.at16lo = p;
+                p += align256(cols * ldt * 2);
+                launch_to_bf16((const float*)db.a, (uint16_t*)db.a16, (uint16_t*)db.a16lo, rows * ld, st);
+                launch_to_bf16((const float*)db.at, (uint16_t*)db.at16, (uint16_t*)db.at16lo, cols * ldt, st);
             }
         }
     }
@@ -244,6 +249,10 @@ void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im
         d.id0 = (int32_t)im.ids.size();
         for (const IdBlock& b : r.op->ids) im.ids.push_back(b);
         d.id1 = (int32_t)im.ids.size();
+        d.cb0 = (int32_t)im.cblk.size();
+        d.cb1 = d.cb0 + (int32_t)r.op->convs.size();
+        d.db0 = (int32_t)im.dblk.size();
+        d.db1 = d.db0 + (int32_t)r.op->dense.size();
         for (size_t j = 0; j < r.op->convs.size(); ++j) {
             if (im.cfwd.size() <= j) {
                 im.cfwd.resize(j + 1);
@@ -306,6 +315,23 @@ void Engine::drop_graph() {
     graph_exec = nullptr;
     graph = nullptr;
     graph_steps = -1;
+    graph_cg = -1;
+}
+
+// CG launches per step for the next check interval: the most CG iterations any
+// running instance used in a step of the last interval, plus two, within
+// [2, cg_max_iters]; fixed at cg_max_iters when adaptation is off.
+void Engine::adapt_cg() {
+    if (!st.cg_adaptive) {
+        cg_launch = st.cg_max_iters;
+        return;
+    }
+    double need = 0.0;
+    for (int i = 0; i < T.ninst; ++i) {
+        const double* sc = scalars(i);
+        if (sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0) need = std::max(need, sc[SC_CGMAXLAST]);
+    }
+    cg_launch = std::max(2, std::min(st.cg_max_iters, (int)need + 2));
 }
 
 int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles) {
@@ -341,9 +367,19 @@ int Engine::build(const std::vector<InstRec>& r) {
     T.ids = (const IdBlock*)put(im.ids.data(), im.ids.size() * sizeof(IdBlock));
     const ConvBlock* cbd = (const ConvBlock*)put(im.cblk.data(), im.cblk.size() * sizeof(ConvBlock));
     const DenseBlock* dbd = (const DenseBlock*)put(im.dblk.data(), im.dblk.size() * sizeof(DenseBlock));
+    T.cblk = cbd;
+    T.dblk = dbd;
     cf.clear(); ca.clear(); df.clear(); da.clear();
-    for (const auto& v : im.cfwd) cf.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size()});
-    for (const auto& v : im.cadj) ca.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size()});
+    const int64_t kcmax = precision == CGS_FP64 ? CONV_KC_MAX_F64 : CONV_KC_MAX_F32;
+    auto slot_kc = [&](const std::vector<ConvTile>& v) {
+        int64_t kc = conv_r(precision);
+        for (const ConvTile& t : v) kc = std::max(kc, std::min(kcmax, im.cblk[t.blk].kpad));
+        return (int)kc;
+    };
+    for (const auto& v : im.cfwd)
+        cf.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(), slot_kc(v)});
+    for (const auto& v : im.cadj)
+        ca.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(), slot_kc(v)});
     for (const auto& v : im.dfwd) df.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
     for (const auto& v : im.dadj) da.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
     if (off > tab_cap) return fail(CGS_ENOMEM, "table overflow");
@@ -359,6 +395,15 @@ int Engine::build(const std::vector<InstRec>& r) {
     T.ny_tiles = (int)im.yt.size();
     T.nseg = (int)im.seg.size();
     T.ninst = (int)im.inst.size();
+    // fused path when every instance is small (and no batched GEMM is in use)
+    use_fused = 0;
+    if (st.fused_max > 0 && !use_gemm && !im.inst.empty()) {
+        bool small = true;
+        for (const InstDesc& d : im.inst) small = small && (d.n + d.m <= (int64_t)st.fused_max);
+        use_fused = small ? 1 : 0;
+    }
+    fused_kc = (int)conv_r(precision);
+    for (const ConvBlock& cb : im.cblk) fused_kc = std::max<int>(fused_kc, (int)std::min(kcmax, cb.kpad));
     CGS_HIP(hipStreamSynchronize(stream));
     drop_graph();
     return CGS_OK;
@@ -373,33 +418,46 @@ char* Engine::yptr(int i, int kind) const {
     return d.base + REGION_HDR + ((size_t)NXV * d.nxs + (size_t)kind * d.nys) * elem_bytes(precision);
 }
 
+// Convolution tiles: matrix cores for FP32 (unless disabled), VALU otherwise.
+void Engine::conv(const ConvLaunch& c, int adj, int out, int in, double sigma, int gate) {
+    if (prec == 1 && st.conv_mfma) launch_conv_mfma(T, c, adj, out, in, sigma, gate, stream);
+    else launch_conv(prec, T, c, adj, out, in, sigma, gate, stream);
+}
+
 void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
     launch_apply_init(prec, T, adj, out, in, base, sigma, gate, stream);
-    for (const auto& c : adj ? ca : cf) launch_conv(prec, T, c, adj, out, in, sigma, gate, stream);
-    for (const auto& d : adj ? da : df) launch_gemv(prec, T, d, adj, out, in, sigma, gate, stream);
+    for (const auto& c : adj ? ca : cf) conv(c, adj, out, in, sigma, gate);
+    if (use_gemm) {
+        // every instance shares the dense blocks: one MFMA GEMM per block
+        for (const DenseBlock& db : recs[0].op->dense)
+            launch_gemm_apply(inst_dev, T.ninst, db, adj, out, in, sigma, gate, gemm_corr, panel_hi,
+                              panel_lo, gemm_part, stream);
+    } else {
+        for (const auto& d : adj ? da : df) launch_gemv(prec, T, d, adj, out, in, sigma, gate, stream);
+    }
 }
 
 // One CG iteration of the Section IV-B listing on (I + A^T A):
 // q = p + A^T (A p); alpha = rr/<p,q>; z += alpha p; r -= alpha q; beta; p = r + beta p.
-void Engine::cg_iter(int z, int gate, int cg_max) {
+void Engine::cg_iter(int z, int gate, int cg_max, int track) {
     apply(0, YT, XP, -1, 1.0, gate);
     apply(1, XQ, YT, XP, 1.0, gate);
     launch_cg_dot(prec, T, XP, XQ, gate, stream);
-    launch_cg_update(prec, T, z, XR, XP, XQ, cg_max, gate, stream);
+    launch_cg_update(prec, T, z, XR, XP, XQ, cg_max, gate, track, stream);
     launch_cg_dir(prec, T, XR, XP, gate, stream);
 }
 
-// One ADMM step of the homogeneous self-dual embedding.
+// One ADMM step of the homogeneous self-dual embedding.  The CG warm start z
+// carries A z (YA) and (I + A^T A) z (XK), updated with every CG step and
+// recomputed exactly at every termination check, so a step applies the
+// operator 1 + 2 * (CG iterations) times.
 void Engine::admm_step() {
     launch_wy(prec, T, G_ADMM, stream);                        // w_y = u_y + v_s
     apply(1, XH, YW, XU, -1.0, G_ADMM);                          // h = u_x - A^T w_y
-    apply(0, YT, XZ, -1, 1.0, G_ADMM);                           // q = z + A^T A z (warm start)
-    apply(1, XQ, YT, XZ, 1.0, G_ADMM);
-    launch_cg_init(prec, T, XZ, XR, XP, XQ, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
-                   st.cg_max_iters, G_ADMM, stream);
-    for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters);
-    apply(0, YZ, XZ, YW, 1.0, G_ADMM);                           // z_y = w_y + A z_x
-    launch_tau_dots(prec, T, st.alpha, stream);                  // u~_tau, tau, kappa
+    launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
+                   st.cg_max_iters, G_ADMM, stream);             // r = h - K z
+    for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1);
+    launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; u~_tau, tau, kappa
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
 }
@@ -408,12 +466,39 @@ void Engine::check() {
     apply(0, YT, XU, -1, 1.0, G_CHECK);                          // A u_x
     apply(1, XT, YU, -1, 1.0, G_CHECK);                          // A^T u_y
     launch_resid(prec, T, st.eps, st.max_iters, stream);
+    refresh();
+}
+
+// Exact recomputation of the carried products of the CG warm start.
+void Engine::refresh() {
+    apply(0, YA, XZ, -1, 1.0, G_ADMM);                           // A z
+    apply(1, XK, YA, XZ, 1.0, G_ADMM);                           // z + A^T (A z)
+}
+
+void Engine::fused_steps(int nsteps, int check) {
+    FusedArgs fa{};
+    fa.nsteps = nsteps;
+    fa.check = check;
+    fa.alpha = st.alpha;
+    fa.eps = st.eps;
+    fa.zeta = st.cg_tol;
+    fa.rate = st.cg_rate;
+    fa.floor_ = st.cg_floor;
+    fa.cg_max = st.cg_max_iters;
+    fa.max_iters = st.max_iters;
+    fa.kc = fused_kc;
+    launch_fused(prec, T, fa, stream);
 }
 
 int Engine::round(int nsteps) {
+    if (use_fused) {
+        fused_steps(nsteps, 1);
+        CGS_HIP(hipGetLastError());
+        return CGS_OK;
+    }
     const bool use_g = st.use_graph && stream != nullptr && nsteps == st.check_every;
     if (use_g) {
-        if (!graph_exec || graph_steps != nsteps) {
+        if (!graph_exec || graph_steps != nsteps || graph_cg != cg_launch) {
             drop_graph();
             CGS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             for (int i = 0; i < nsteps; ++i) admm_step();
@@ -424,6 +509,7 @@ int Engine::round(int nsteps) {
             graph = g;
             CGS_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
             graph_steps = nsteps;
+            graph_cg = cg_launch;
         }
         CGS_HIP(hipGraphLaunch(graph_exec, stream));
     } else {
@@ -451,7 +537,7 @@ int Engine::setup() {
     int it = 0;
     while (it < st.setup_max_iters) {
         const int nb = std::min(8, st.setup_max_iters - it);
-        for (int j = 0; j < nb; ++j) cg_iter(XG, G_SETUP_CG, st.setup_max_iters);
+        for (int j = 0; j < nb; ++j) cg_iter(XG, G_SETUP_CG, st.setup_max_iters, 0);
         it += nb;
         CGS_TRY(fetch_scalars());
         bool any = false;

@@ -132,10 +132,20 @@ class Engine {
     std::vector<ConvLaunch> cf, ca;
     std::vector<DenseLaunch> df, da;
     int cg_launch = 1;
+    // fused path: one workgroup per instance runs whole steps (small instances)
+    int use_fused = 0;
+    int fused_kc = 8;
+    // batched BF16 MFMA path for dense blocks shared by every instance
+    int use_gemm = 0;
+    int gemm_corr = 0;           // 1: add the refinement products (hi x lo)
+    uint16_t* panel_hi = nullptr;
+    uint16_t* panel_lo = nullptr;
+    float* gemm_part = nullptr;
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_steps = -1;
+    int graph_cg = -1;
 
     ~Engine();
     int init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles);
@@ -145,9 +155,13 @@ class Engine {
 
     // ---- device work (enqueue only)
     void apply(int adj, int out, int in, int base, double sigma, int gate);
-    void cg_iter(int z, int gate, int cg_max);
+    void conv(const ConvLaunch& c, int adj, int out, int in, double sigma, int gate);
+    void cg_iter(int z, int gate, int cg_max, int track);
     void admm_step();
+    void fused_steps(int nsteps, int check);
     void check();
+    void refresh();
+    void adapt_cg();
     // ---- host loops
     int setup();                  // instances with phase 0 (synchronises)
     int round(int nsteps);        // nsteps ADMM steps + termination test (enqueue)

@@ -5,11 +5,13 @@
 //    in one instance; a workgroup first reads its instance's gate flags and
 //    leaves at once when the instance does not take part in this step.
 //  * Reductions (dot products, norms) are deterministic: each workgroup folds
-//    its tile in a fixed thread/wave order into FP64 partials; the last
-//    workgroup of an instance to arrive (atomic arrival counter) sums the
-//    instance's partials in tile order and finishes the scalar work (CG alpha
-//    and beta, tau/kappa, residuals).  No floating-point atomics are used, so
-//    an instance's numbers do not depend on the other instances of a launch.
+//    its tile in a fixed thread/wave order into FP64 partials, and a finalize
+//    kernel (one workgroup per instance) sums the instance's partials in tile
+//    order and finishes the scalar work (CG alpha and beta, tau/kappa,
+//    residuals).  No atomics and no device-wide fences are used inside a
+//    kernel (on a multi-XCD part a device-scope fence writes back and
+//    invalidates the XCD's L2), so an instance's numbers do not depend on the
+//    other instances of a launch.
 //  * Vectors are in the working precision T (float or double); every scalar of
 //    the method (tau, kappa, eta, CG alpha/beta, norms, residuals) is FP64.
 #include <hip/hip_runtime.h>
@@ -18,107 +20,9 @@
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "device_common.hpp"
 
 namespace cgs {
-
-#define DEVI __device__ __forceinline__
-
-// ---------------------------------------------------------------- helpers
-template <typename T>
-DEVI T* xvec(const InstDesc& d, int k) {
-    return reinterpret_cast<T*>(d.base + REGION_HDR) + (int64_t)k * d.nxs;
-}
-template <typename T>
-DEVI T* yvec(const InstDesc& d, int k) {
-    return reinterpret_cast<T*>(d.base + REGION_HDR) + (int64_t)NXV * d.nxs + (int64_t)k * d.nys;
-}
-DEVI double* scal(const InstDesc& d) { return reinterpret_cast<double*>(d.base); }
-DEVI int* counters(const InstDesc& d) { return reinterpret_cast<int*>(d.base + NSC * 8); }
-
-DEVI bool gate_ok(const double* sc, int gate) {
-    switch (gate) {
-        case G_ALL: return true;
-        case G_SETUP: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0;
-        case G_SETUP_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0 && sc[SC_CGACT] != 0.0;
-        case G_ADMM:
-        case G_CHECK: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0;
-        case G_ADMM_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0 && sc[SC_CGACT] != 0.0;
-        case G_ANY_CG: return sc[SC_CGACT] != 0.0;
-        default: return false;
-    }
-}
-
-DEVI double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Sum over the workgroup in a fixed order; the result is valid in thread 0.
-template <int NT>
-DEVI double block_sum(double v, double* sh) {
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) sh[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NT / 64; ++i) r += sh[i];
-    }
-    return r;
-}
-
-DEVI double load_coherent(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Arrival at a per-instance counter.  Thread 0 must have stored the
-// workgroup's partials before the call.  Returns true in every thread of the
-// workgroup that arrived last; that workgroup resets the counter when done.
-DEVI bool arrive_last(int* counter, int expected) {
-    __shared__ int flag;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int prev = atomicAdd(counter, 1);
-        flag = (prev == expected - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-// Fixed-order sum of partial slot j over tiles [t0, t1).
-template <int NT>
-DEVI double sum_parts(const double* part, int t0, int t1, int j, double* sh) {
-    double s = 0.0;
-    for (int i = t0 + (int)threadIdx.x; i < t1; i += NT) s += load_coherent(part + 4 * (int64_t)i + j);
-    return block_sum<NT>(s, sh);
-}
-
-// Tile of a kernel that walks the X tiles and then the Y tiles.
-struct XYTile {
-    VecTile t;
-    bool is_y;
-    int index;   // index in its own table
-};
-DEVI XYTile xy_tile(const Tables& tb) {
-    XYTile r;
-    const int b = blockIdx.x;
-    if (b < tb.nx_tiles) {
-        r.t = tb.xt[b];
-        r.is_y = false;
-        r.index = b;
-    } else {
-        r.t = tb.yt[b - tb.nx_tiles];
-        r.is_y = true;
-        r.index = b - tb.nx_tiles;
-    }
-    return r;
-}
 
 // ---------------------------------------------------------------- operator: identity part + base
 template <typename T>
@@ -127,9 +31,9 @@ __global__ __launch_bounds__(VEC_NT) void k_apply_init(Tables tb, int adj, int o
     const VecTile tl = adj ? tb.xt[blockIdx.x] : tb.yt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
-    T* o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
-    const T* src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
-    const T* bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
+    gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
+    gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
+    gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
     const int64_t lo = tl.start, hi = tl.start + tl.len;
     for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
         double v = bs ? (double)bs[i] : 0.0;
@@ -143,95 +47,21 @@ __global__ __launch_bounds__(VEC_NT) void k_apply_init(Tables tb, int adj, int o
     }
 }
 
-// ---------------------------------------------------------------- operator: convolution
-// Direct full convolution and its adjoint (valid correlation) in one
-// correlation form:  out[o] += s * sum_t w[t] * in[o + off + t]  with
-//   A x : w = reversed taps, off = -(k-1), in = x (zero outside [0, n_in));
-//   A^T y: w = taps,          off = 0,      in = y.
-// A workgroup computes CONV_NT * R consecutive outputs; each thread keeps R
-// outputs in registers and slides a 2R-wide register window over an LDS copy
-// of the input; taps are staged in LDS in chunks of KC and read as broadcasts.
-constexpr int CONV_NT = 256;
-template <typename T> struct ConvCfg;
-template <> struct ConvCfg<float> { static constexpr int R = 8, KC = 512; };
-template <> struct ConvCfg<double> { static constexpr int R = 4, KC = 256; };
-static_assert(CONV_NT * ConvCfg<float>::R == CONV_TILE_F32 && ConvCfg<float>::R == CONV_R_F32, "conv tile");
-static_assert(CONV_NT * ConvCfg<double>::R == CONV_TILE_F64 && ConvCfg<double>::R == CONV_R_F64, "conv tile");
-
 template <typename T>
 __global__ __launch_bounds__(CONV_NT) void k_conv(Tables tb, ConvLaunch cl, int adj, int out, int in,
                                                   double sigma, int gate) {
-    constexpr int R = ConvCfg<T>::R, KC = ConvCfg<T>::KC, TILE = CONV_NT * R;
-    constexpr int WIN = TILE + KC + 2 * R;
-    __shared__ __align__(16) T win[WIN];
-    __shared__ __align__(16) T taps[KC];
+    extern __shared__ __align__(16) unsigned char conv_smem[];
     const ConvTile tl = cl.tiles[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
     const ConvBlock cb = cl.blocks[tl.blk];
-    int64_t n_out, n_in, off;
-    const T* w;
-    T* o;
-    const T* src;
-    if (!adj) {
-        n_out = cb.n_in + cb.k - 1;
-        n_in = cb.n_in;
-        off = -(cb.k - 1);
-        w = static_cast<const T*>(cb.w_fwd);
-        o = yvec<T>(d, out) + cb.row0;
-        src = xvec<T>(d, in) + cb.col0;
-    } else {
-        n_out = cb.n_in;
-        n_in = cb.n_in + cb.k - 1;
-        off = 0;
-        w = static_cast<const T*>(cb.w_adj);
-        o = xvec<T>(d, out) + cb.col0;
-        src = yvec<T>(d, in) + cb.row0;
-    }
-    const int tid = threadIdx.x;
-    const int64_t ot = tl.start;
-    T acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = T(0);
+    conv_tile<T, CONV_NT>(d, cb, adj, out, in, sigma, tl.start, cl.kc, conv_smem);
+}
 
-    for (int64_t t0 = 0; t0 < cb.kpad; t0 += KC) {
-        const int kc = (int)((cb.kpad - t0) < KC ? (cb.kpad - t0) : KC);   // multiple of R
-        __syncthreads();
-        const int64_t w0 = ot + off + t0;
-        for (int i = tid; i < TILE + kc + R; i += CONV_NT) {
-            const int64_t g = w0 + i;
-            win[i] = (g >= 0 && g < n_in) ? src[g] : T(0);
-        }
-        for (int i = tid; i < kc; i += CONV_NT) taps[i] = w[t0 + i];
-        __syncthreads();
-        const T* wp = win + tid * R;
-        T cur[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) cur[r] = wp[r];
-        for (int tt = 0; tt < kc; tt += R) {
-            T nxt[R], tw[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) nxt[r] = wp[tt + R + r];
-#pragma unroll
-            for (int u = 0; u < R; ++u) tw[u] = taps[tt + u];
-#pragma unroll
-            for (int u = 0; u < R; ++u) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T xv = (r + u < R) ? cur[r + u] : nxt[r + u - R];
-                    acc[r] = fma(tw[u], xv, acc[r]);
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) cur[r] = nxt[r];
-        }
-    }
-    const double s = sigma * cb.scale;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t oi = ot + (int64_t)tid * R + r;
-        if (oi < n_out) o[oi] = (T)((double)o[oi] + s * (double)acc[r]);
-    }
+size_t conv_smem_bytes(int prec, int kc) {
+    const int R = prec == 0 ? CONV_R_F64 : CONV_R_F32;
+    const int tile = prec == 0 ? CONV_TILE_F64 : CONV_TILE_F32;
+    return (size_t)(tile + 2 * kc + 2 * R) * (prec == 0 ? 8 : 4);
 }
 
 // ---------------------------------------------------------------- operator: dense block
@@ -241,17 +71,6 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(Tables tb, ConvLaunch cl, int 
 // transpose, so both directions read rows contiguously.
 constexpr int GEMV_NT = 256;
 constexpr int GEMV_RB = DENSE_ROWS;
-
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
-
-template <typename T>
-DEVI void vec_get(const typename Vec16<T>::type& v, T* out);
-template <>
-DEVI void vec_get<float>(const float4& v, float* o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
-template <>
-DEVI void vec_get<double>(const double2& v, double* o) { o[0] = v.x; o[1] = v.y; }
 
 template <typename T>
 __global__ __launch_bounds__(GEMV_NT) void k_gemv(Tables tb, DenseLaunch dl, int adj, int out, int in,
@@ -263,25 +82,25 @@ __global__ __launch_bounds__(GEMV_NT) void k_gemv(Tables tb, DenseLaunch dl, int
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
     const DenseBlock db = dl.blocks[tl.blk];
-    const T* a;
+    gptr<const T> a;
     int64_t ld, ncols;
-    T* o;
-    const T* x;
+    gptr<T> o;
+    gptr<const T> x;
     if (!adj) {
-        a = static_cast<const T*>(db.a);
+        a = (gptr<const T>)db.a;
         ld = db.ld;
         ncols = db.cols;
         o = yvec<T>(d, out) + db.row0;
         x = xvec<T>(d, in) + db.col0;
     } else {
-        a = static_cast<const T*>(db.at);
+        a = (gptr<const T>)db.at;
         ld = db.ldt;
         ncols = db.rows;
         o = xvec<T>(d, out) + db.col0;
         x = yvec<T>(d, in) + db.row0;
     }
     const int nr = tl.nr;
-    const T* arow = a + tl.r0 * ld;
+    gptr<const T> arow = a + tl.r0 * ld;
     double acc[GEMV_RB];
 #pragma unroll
     for (int r = 0; r < GEMV_RB; ++r) acc[r] = 0.0;
@@ -293,7 +112,7 @@ __global__ __launch_bounds__(GEMV_NT) void k_gemv(Tables tb, DenseLaunch dl, int
 #pragma unroll
         for (int r = 0; r < GEMV_RB; ++r) {
             if (r < nr) {
-                const V av = *reinterpret_cast<const V*>(arow + r * ld + v * VW);
+                const V av = *(gptr<const V>)(arow + r * ld + v * VW);
                 T ae[VW];
                 vec_get<T>(av, ae);
 #pragma unroll
@@ -312,7 +131,7 @@ __global__ __launch_bounds__(GEMV_NT) void k_gemv(Tables tb, DenseLaunch dl, int
     for (int r = 0; r < GEMV_RB; ++r) {
         const double tot = block_sum<GEMV_NT>(acc[r], sh[r]);
         if (threadIdx.x == 0 && r < nr) {
-            T* op = o + tl.r0 + r;
+            gptr<T> op = o + tl.r0 + r;
             *op = (T)((double)*op + s * tot);
         }
     }
@@ -326,12 +145,12 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_init(Tables tb, int z, int r, int
     __shared__ double sh[VEC_NT / 64];
     const VecTile tl = tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
-    double* sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
-    T* rv = xvec<T>(d, r);
-    T* pv = xvec<T>(d, p);
-    const T* qv = xvec<T>(d, q);
-    const T* hv = xvec<T>(d, h);
+    gptr<T> rv = xvec<T>(d, r);
+    gptr<T> pv = xvec<T>(d, p);
+    gptr<const T> qv = xvec<T>(d, q);
+    gptr<const T> hv = xvec<T>(d, h);
     double s0 = 0.0, s1 = 0.0;
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) {
         const double hi = (double)hv[i];
@@ -348,23 +167,6 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_init(Tables tb, int z, int r, int
         part[0] = s0;
         part[1] = s1;
     }
-    if (arrive_last(counters(d), d.xt1 - d.xt0)) {
-        const double rr = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        const double hh = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 1, sh);
-        if (threadIdx.x == 0) {
-            const double hn = sqrt(hh);
-            const double k = (gate == G_SETUP || gate == G_SETUP_CG) ? 0.0 : sc[SC_ITER];
-            double rel = zeta > 0.0 ? zeta / pow(k + 1.0, rate) : 0.0;
-            rel = rel > floor_ ? rel : floor_;
-            const double tol = hn * rel;
-            sc[SC_RR] = rr;
-            sc[SC_HN] = hn;
-            sc[SC_CGTOL] = tol;
-            sc[SC_CGIT] = 0.0;
-            sc[SC_CGACT] = (cg_max > 0 && sqrt(rr) > tol && std::isfinite(rr)) ? 1.0 : 0.0;
-            counters(d)[0] = 0;
-        }
-    }
 }
 
 template <typename T>
@@ -372,66 +174,52 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
     __shared__ double sh[VEC_NT / 64];
     const VecTile tl = tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
-    double* sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
-    const T* pv = xvec<T>(d, p);
-    const T* qv = xvec<T>(d, q);
+    gptr<const T> pv = xvec<T>(d, p);
+    gptr<const T> qv = xvec<T>(d, q);
     double s0 = 0.0;
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
         s0 = fma((double)pv[i], (double)qv[i], s0);
     s0 = block_sum<VEC_NT>(s0, sh);
     if (threadIdx.x == 0) tb.xpart[4 * (int64_t)blockIdx.x] = s0;
-    if (arrive_last(counters(d), d.xt1 - d.xt0)) {
-        const double pq = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        if (threadIdx.x == 0) {
-            sc[SC_PQ] = pq;
-            const double al = sc[SC_RR] / pq;
-            if (pq > 0.0 && std::isfinite(al)) {
-                sc[SC_ALPHA] = al;
-            } else {
-                sc[SC_ALPHA] = 0.0;
-                sc[SC_CGACT] = 0.0;
-            }
-            counters(d)[0] = 0;
-        }
-    }
 }
 
+// z += alpha p; r -= alpha q; partial ||r||^2; with `track`, the carried
+// products follow z:  K z += alpha q (X tiles) and A z += alpha A p (Y tiles,
+// A p sits in YT).
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q,
-                                                      int cg_max, int gate) {
+                                                      int cg_max, int gate, int track) {
     __shared__ double sh[VEC_NT / 64];
-    const VecTile tl = tb.xt[blockIdx.x];
-    const InstDesc d = tb.inst[tl.inst];
-    double* sc = scal(d);
+    const XYTile xt = xy_tile(tb);
+    const InstDesc d = tb.inst[xt.t.inst];
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
     const double al = sc[SC_ALPHA];
-    T* zv = xvec<T>(d, z);
-    T* rv = xvec<T>(d, r);
-    const T* pv = xvec<T>(d, p);
-    const T* qv = xvec<T>(d, q);
+    const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     double s0 = 0.0;
-    for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) {
-        zv[i] = (T)fma(al, (double)pv[i], (double)zv[i]);
-        const T ri = (T)fma(-al, (double)qv[i], (double)rv[i]);
-        rv[i] = ri;
-        s0 = fma((double)ri, (double)ri, s0);
-    }
-    s0 = block_sum<VEC_NT>(s0, sh);
-    if (threadIdx.x == 0) tb.xpart[4 * (int64_t)blockIdx.x] = s0;
-    if (arrive_last(counters(d), d.xt1 - d.xt0)) {
-        const double rr = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        if (threadIdx.x == 0) {
-            const double prev = sc[SC_RR];
-            sc[SC_BETA] = prev > 0.0 ? rr / prev : 0.0;
-            sc[SC_RR] = rr;
-            sc[SC_CGIT] += 1.0;
-            sc[SC_CGTOT] += 1.0;
-            if (gate == G_SETUP_CG) sc[SC_SETUPIT] += 1.0;
-            const bool more = std::isfinite(rr) && sqrt(rr) > sc[SC_CGTOL] && sc[SC_CGIT] < (double)cg_max;
-            sc[SC_CGACT] = more ? 1.0 : 0.0;
-            counters(d)[0] = 0;
+    if (!xt.is_y) {
+        gptr<T> zv = xvec<T>(d, z);
+        gptr<T> rv = xvec<T>(d, r);
+        gptr<const T> pv = xvec<T>(d, p);
+        gptr<const T> qv = xvec<T>(d, q);
+        gptr<T> kz = xvec<T>(d, XK);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
+            const double qi = (double)qv[i];
+            zv[i] = (T)fma(al, (double)pv[i], (double)zv[i]);
+            const T ri = (T)fma(-al, qi, (double)rv[i]);
+            rv[i] = ri;
+            if (track) kz[i] = (T)fma(al, qi, (double)kz[i]);
+            s0 = fma((double)ri, (double)ri, s0);
         }
+        s0 = block_sum<VEC_NT>(s0, sh);
+        if (threadIdx.x == 0) tb.xpart[4 * (int64_t)xt.index] = s0;
+    } else {
+        gptr<T> az = yvec<T>(d, YA);
+        gptr<const T> ap = yvec<T>(d, YT);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT)
+            az[i] = (T)fma(al, (double)ap[i], (double)az[i]);
     }
 }
 
@@ -439,11 +227,11 @@ template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_cg_dir(Tables tb, int r, int p, int gate) {
     const VecTile tl = tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
-    const double* sc = scal(d);
+    gptr<const double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
     const double be = sc[SC_BETA];
-    const T* rv = xvec<T>(d, r);
-    T* pv = xvec<T>(d, p);
+    gptr<const T> rv = xvec<T>(d, r);
+    gptr<T> pv = xvec<T>(d, p);
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
         pv[i] = (T)fma(be, (double)pv[i], (double)rv[i]);
 }
@@ -454,54 +242,41 @@ __global__ __launch_bounds__(VEC_NT) void k_wy(Tables tb, int gate) {
     const VecTile tl = tb.yt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
-    const T* u = yvec<T>(d, YU);
-    const T* v = yvec<T>(d, YV);
-    T* w = yvec<T>(d, YW);
+    gptr<const T> u = yvec<T>(d, YU);
+    gptr<const T> v = yvec<T>(d, YV);
+    gptr<T> w = yvec<T>(d, YW);
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
         w[i] = (T)((double)u[i] + (double)v[i]);
 }
 
 // u~_tau = (w_tau + c^T z_x + b^T z_y) / eta  (exact solve of (I+Q) u~ = w,
 // last row), then the tau/kappa part of relaxation, projection and dual update.
+// With `form_zy`, the Y tiles first form z_y = w_y + A z from the carried A z.
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha) {
+__global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha, int form_zy) {
     __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
-    double* sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
-    const T* a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
-    const T* b = xt.is_y ? yvec<T>(d, YZ) : xvec<T>(d, XZ);
+    gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
+    gptr<T> b = xt.is_y ? yvec<T>(d, YZ) : xvec<T>(d, XZ);
     double s0 = 0.0;
-    for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
-        s0 = fma((double)a[i], (double)b[i], s0);
+    if (xt.is_y && form_zy) {
+        gptr<const T> wy = yvec<T>(d, YW);
+        gptr<const T> az = yvec<T>(d, YA);
+        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT) {
+            const T zy = (T)((double)wy[i] + (double)az[i]);
+            b[i] = zy;
+            s0 = fma((double)a[i], (double)zy, s0);
+        }
+    } else {
+        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
+            s0 = fma((double)a[i], (double)b[i], s0);
+    }
     s0 = block_sum<VEC_NT>(s0, sh);
     double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
     if (threadIdx.x == 0) part[0] = s0;
-    if (arrive_last(counters(d), (d.xt1 - d.xt0) + (d.yt1 - d.yt0))) {
-        const double cz = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        const double bz = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 0, sh);
-        if (threadIdx.x == 0) {
-            const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
-            const double ut = (tau + kap + cz + bz) / sc[SC_ETA];
-            const double ubar = alpha * ut + (1.0 - alpha) * tau;
-            const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
-            sc[SC_UT] = ut;
-            sc[SC_KAPPA] = kap - ubar + tnew;
-            sc[SC_TAU] = tnew;
-            sc[SC_ITER] += 1.0;
-            counters(d)[0] = 0;
-        }
-    }
-}
-
-// relaxed point minus v for a Y entry
-template <typename T>
-DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, double& ubar) {
-    const double uy = (double)yvec<T>(d, YU)[i];
-    const double ut_y = (double)yvec<T>(d, YZ)[i] - ut * (double)yvec<T>(d, YG)[i];
-    ubar = alpha * ut_y + (1.0 - alpha) * uy;
-    return ubar - (double)yvec<T>(d, YV)[i];
 }
 
 template <typename T>
@@ -510,7 +285,7 @@ __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
     const VecTile tl = tb.yt[blockIdx.x];
     if (tl.seg < 0) return;
     const InstDesc d = tb.inst[tl.inst];
-    const double* sc = scal(d);
+    gptr<const double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
     const SocSeg sg = tb.seg[tl.seg];
     const double ut = sc[SC_UT];
@@ -523,35 +298,28 @@ __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
     }
     s0 = block_sum<VEC_NT>(s0, sh);
     if (threadIdx.x == 0) tb.ypart[4 * (int64_t)blockIdx.x] = s0;
-    if (arrive_last(tb.seg_cnt + tl.seg, sg.ntiles)) {
-        const double ss = sum_parts<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 0, sh);
-        if (threadIdx.x == 0) {
-            tb.seg_val[2 * tl.seg + 1] = ss;
-            tb.seg_cnt[tl.seg] = 0;
-        }
-    }
 }
 
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
-    const double* sc = scal(d);
+    gptr<const double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
     const double ut = sc[SC_UT];
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     if (!xt.is_y) {
-        T* ux = xvec<T>(d, XU);
-        const T* zx = xvec<T>(d, XZ);
-        const T* gx = xvec<T>(d, XG);
+        gptr<T> ux = xvec<T>(d, XU);
+        gptr<const T> zx = xvec<T>(d, XZ);
+        gptr<const T> gx = xvec<T>(d, XG);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             const double utx = (double)zx[i] - ut * (double)gx[i];
             ux[i] = (T)(alpha * utx + (1.0 - alpha) * (double)ux[i]);
         }
         return;
     }
-    T* uy = yvec<T>(d, YU);
-    T* vs = yvec<T>(d, YV);
+    gptr<T> uy = yvec<T>(d, YU);
+    gptr<T> vs = yvec<T>(d, YV);
     if (xt.t.seg < 0) {
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             double ub;
@@ -563,8 +331,8 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         return;
     }
     const SocSeg sg = tb.seg[xt.t.seg];
-    const double t = load_coherent(tb.seg_val + 2 * xt.t.seg);
-    const double nz = sqrt(load_coherent(tb.seg_val + 2 * xt.t.seg + 1));
+    const double t = tb.seg_val[2 * xt.t.seg];
+    const double nz = sqrt(tb.seg_val[2 * xt.t.seg + 1]);
     // Pi(t, z): (t, z) if ||z|| <= t; 0 if ||z|| <= -t; ((t+||z||)/2)(1, z/||z||) otherwise
     int mode;
     double a = 0.0;
@@ -593,16 +361,16 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
     __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
-    double* sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_CHECK)) return;
     const double tau = sc[SC_TAU];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     if (xt.is_y) {
-        const T* au = yvec<T>(d, YT);
-        const T* vs = yvec<T>(d, YV);
-        const T* b = yvec<T>(d, YB);
-        const T* uy = yvec<T>(d, YU);
+        gptr<const T> au = yvec<T>(d, YT);
+        gptr<const T> vs = yvec<T>(d, YV);
+        gptr<const T> b = yvec<T>(d, YB);
+        gptr<const T> uy = yvec<T>(d, YU);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             const double e = (double)au[i] + (double)vs[i];
             const double rp = e - tau * (double)b[i];
@@ -611,9 +379,9 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
             s2 = fma((double)b[i], (double)uy[i], s2);
         }
     } else {
-        const T* aty = xvec<T>(d, XT);
-        const T* c = xvec<T>(d, XC);
-        const T* ux = xvec<T>(d, XU);
+        gptr<const T> aty = xvec<T>(d, XT);
+        gptr<const T> c = xvec<T>(d, XC);
+        gptr<const T> ux = xvec<T>(d, XU);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             const double e = (double)aty[i];
             const double rd = e + tau * (double)c[i];
@@ -631,18 +399,108 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
         part[1] = s1;
         part[2] = s2;
     }
-    if (arrive_last(counters(d), (d.xt1 - d.xt0) + (d.yt1 - d.yt0))) {
-        const double y0 = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 0, sh);
-        const double y1 = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 1, sh);
-        const double y2 = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 2, sh);
-        const double x0 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        const double x1 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 1, sh);
-        const double x2 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 2, sh);
-        if (threadIdx.x == 0) {
-            const double kap = sc[SC_KAPPA];
+}
+
+
+// ---------------------------------------------------------------- per-instance finalize
+// One workgroup per instance sums the partials of the kernel just before it in
+// tile order and finishes the scalar work of the method.
+enum FinMode : int {
+    FIN_CG_INIT = 0,   // rr = ||r||^2, ||h||; CG tolerance and start flag
+    FIN_CG_DOT,        // alpha = rr / <p, q>
+    FIN_CG_UPDATE,     // rr', beta, stop test
+    FIN_TAU,           // u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta; tau, kappa
+    FIN_RESID,         // residuals, gap, certificates, status
+    FIN_NORMS,         // ||b||, ||c||
+    FIN_ETA            // eta = 1 + c^T g_x + b^T g_y; phase -> iterating
+};
+struct FinArgs {
+    double a0, a1, a2;
+    int i0, i1;
+};
+
+__global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int gate, FinArgs fa) {
+    __shared__ double sh[VEC_NT / 64];
+    const InstDesc d = tb.inst[blockIdx.x];
+    gptr<double> sc = scal(d);
+    if (!gate_ok(sc, gate)) return;
+    double x0 = 0, x1 = 0, x2 = 0, y0 = 0, y1 = 0, y2 = 0;
+    const bool use_x = true;
+    const bool use_y = mode == FIN_TAU || mode == FIN_RESID || mode == FIN_NORMS || mode == FIN_ETA;
+    const int nslot = (mode == FIN_RESID) ? 3 : (mode == FIN_CG_INIT ? 2 : 1);
+    if (use_x) {
+        x0 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
+        if (nslot > 1) x1 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 1, sh);
+        if (nslot > 2) x2 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 2, sh);
+    }
+    if (use_y) {
+        y0 = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 0, sh);
+        if (nslot > 1) y1 = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 1, sh);
+        if (nslot > 2) y2 = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 2, sh);
+    }
+    if (threadIdx.x != 0) return;
+    switch (mode) {
+        case FIN_CG_INIT: {
+            // tol = ||h|| max(floor, zeta / (k+1)^rate) at ADMM step k (k = 0 in setup)
+            const double zeta = fa.a0, rate = fa.a1, floor_ = fa.a2;
+            const int cg_max = fa.i0;
+            const double hn = sqrt(x1);
+            const double k = (gate == G_SETUP || gate == G_SETUP_CG) ? 0.0 : sc[SC_ITER];
+            double rel = zeta > 0.0 ? zeta / pow(k + 1.0, rate) : 0.0;
+            rel = rel > floor_ ? rel : floor_;
+            const double tol = hn * rel;
+            sc[SC_RR] = x0;
+            sc[SC_HN] = hn;
+            sc[SC_CGTOL] = tol;
+            sc[SC_CGIT] = 0.0;
+            sc[SC_CGACT] = (cg_max > 0 && sqrt(x0) > tol && std::isfinite(x0)) ? 1.0 : 0.0;
+            break;
+        }
+        case FIN_CG_DOT: {
+            sc[SC_PQ] = x0;
+            const double al = sc[SC_RR] / x0;
+            if (x0 > 0.0 && std::isfinite(al)) {
+                sc[SC_ALPHA] = al;
+            } else {
+                sc[SC_ALPHA] = 0.0;
+                sc[SC_CGACT] = 0.0;
+            }
+            break;
+        }
+        case FIN_CG_UPDATE: {
+            const int cg_max = fa.i0;
+            const double prev = sc[SC_RR];
+            sc[SC_BETA] = prev > 0.0 ? x0 / prev : 0.0;
+            sc[SC_RR] = x0;
+            sc[SC_CGIT] += 1.0;
+            sc[SC_CGTOT] += 1.0;
+            if (sc[SC_CGIT] > sc[SC_CGMAX]) sc[SC_CGMAX] = sc[SC_CGIT];
+            if (gate == G_SETUP_CG) sc[SC_SETUPIT] += 1.0;
+            const bool more = std::isfinite(x0) && sqrt(x0) > sc[SC_CGTOL] && sc[SC_CGIT] < (double)cg_max;
+            sc[SC_CGACT] = more ? 1.0 : 0.0;
+            break;
+        }
+        case FIN_TAU: {
+            const double alpha = fa.a0;
+            const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
+            const double ut = (tau + kap + x0 + y0) / sc[SC_ETA];
+            const double ubar = alpha * ut + (1.0 - alpha) * tau;
+            const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
+            sc[SC_UT] = ut;
+            sc[SC_KAPPA] = kap - ubar + tnew;
+            sc[SC_TAU] = tnew;
+            sc[SC_ITER] += 1.0;
+            break;
+        }
+        case FIN_RESID: {
+            const double eps = fa.a0;
+            const int max_iters = fa.i0;
+            const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
             double status = 0.0;
             sc[SC_CUX] = x2;
             sc[SC_BUY] = y2;
+            sc[SC_CGMAXLAST] = sc[SC_CGMAX];
+            sc[SC_CGMAX] = 0.0;
             const bool finite = std::isfinite(y0) && std::isfinite(y1) && std::isfinite(y2) &&
                                 std::isfinite(x0) && std::isfinite(x1) && std::isfinite(x2) &&
                                 std::isfinite(tau) && std::isfinite(kap);
@@ -673,9 +531,30 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
                 sc[SC_STATUS] = status;
                 sc[SC_ACTIVE] = 0.0;
             }
-            counters(d)[0] = 0;
+            break;
         }
+        case FIN_NORMS:
+            sc[SC_NB] = sqrt(y0);
+            sc[SC_NC] = sqrt(x0);
+            break;
+        case FIN_ETA:
+            sc[SC_ETA] = 1.0 + x0 + y0;
+            sc[SC_PHASE] = 1.0;
+            sc[SC_CGACT] = 0.0;
+            break;
+        default:
+            break;
     }
+}
+
+// Tail sum of squares of every second-order cone (one workgroup per cone).
+__global__ __launch_bounds__(VEC_NT) void k_finalize_soc(Tables tb) {
+    __shared__ double sh[VEC_NT / 64];
+    const SocSeg sg = tb.seg[blockIdx.x];
+    const InstDesc d = tb.inst[sg.inst];
+    if (!gate_ok(scal(d), G_ADMM)) return;
+    const double ss = sum_parts<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 0, sh);
+    if (threadIdx.x == 0) tb.seg_val[2 * blockIdx.x + 1] = ss;
 }
 
 // ---------------------------------------------------------------- setup
@@ -686,23 +565,27 @@ __global__ __launch_bounds__(VEC_NT) void k_reset(Tables tb, int only) {
     const InstDesc d = tb.inst[xt.t.inst];
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     if (xt.is_y) {
-        T* uy = yvec<T>(d, YU);
-        T* vs = yvec<T>(d, YV);
+        gptr<T> uy = yvec<T>(d, YU);
+        gptr<T> vs = yvec<T>(d, YV);
+        gptr<T> az = yvec<T>(d, YA);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             uy[i] = T(0);
             vs[i] = T(0);
+            az[i] = T(0);
         }
     } else {
-        T* ux = xvec<T>(d, XU);
-        T* zx = xvec<T>(d, XZ);
-        T* gx = xvec<T>(d, XG);
+        gptr<T> ux = xvec<T>(d, XU);
+        gptr<T> zx = xvec<T>(d, XZ);
+        gptr<T> gx = xvec<T>(d, XG);
+        gptr<T> kz = xvec<T>(d, XK);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             ux[i] = T(0);
             zx[i] = T(0);
             gx[i] = T(0);
+            kz[i] = T(0);
         }
         if (xt.index == d.xt0 && threadIdx.x == 0) {
-            double* sc = scal(d);
+            gptr<double> sc = scal(d);
             for (int j = 0; j < NSC; ++j) sc[j] = 0.0;
             sc[SC_TAU] = 1.0;
             sc[SC_KAPPA] = 1.0;
@@ -719,24 +602,15 @@ __global__ __launch_bounds__(VEC_NT) void k_norms(Tables tb, int gate) {
     __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
-    double* sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
-    const T* v = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
+    gptr<const T> v = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
     double s0 = 0.0;
     for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
         s0 = fma((double)v[i], (double)v[i], s0);
     s0 = block_sum<VEC_NT>(s0, sh);
     double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
     if (threadIdx.x == 0) part[0] = s0;
-    if (arrive_last(counters(d), (d.xt1 - d.xt0) + (d.yt1 - d.yt0))) {
-        const double cc = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        const double bb = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 0, sh);
-        if (threadIdx.x == 0) {
-            sc[SC_NB] = sqrt(bb);
-            sc[SC_NC] = sqrt(cc);
-            counters(d)[0] = 0;
-        }
-    }
 }
 
 // eta = 1 + c^T g_x + b^T g_y; the instance then starts iterating.
@@ -745,26 +619,16 @@ __global__ __launch_bounds__(VEC_NT) void k_eta(Tables tb) {
     __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
-    double* sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_SETUP)) return;
-    const T* a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
-    const T* g = xt.is_y ? yvec<T>(d, YG) : xvec<T>(d, XG);
+    gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
+    gptr<const T> g = xt.is_y ? yvec<T>(d, YG) : xvec<T>(d, XG);
     double s0 = 0.0;
     for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
         s0 = fma((double)a[i], (double)g[i], s0);
     s0 = block_sum<VEC_NT>(s0, sh);
     double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
     if (threadIdx.x == 0) part[0] = s0;
-    if (arrive_last(counters(d), (d.xt1 - d.xt0) + (d.yt1 - d.yt0))) {
-        const double cg = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
-        const double bg = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, 0, sh);
-        if (threadIdx.x == 0) {
-            sc[SC_ETA] = 1.0 + cg + bg;
-            sc[SC_PHASE] = 1.0;
-            sc[SC_CGACT] = 0.0;
-            counters(d)[0] = 0;
-        }
-    }
 }
 
 template <typename T>
@@ -772,7 +636,7 @@ __global__ __launch_bounds__(VEC_NT) void k_fill(Tables tb, int is_y, int kind, 
     const VecTile tl = is_y ? tb.yt[blockIdx.x] : tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
-    T* o = is_y ? yvec<T>(d, kind) : xvec<T>(d, kind);
+    gptr<T> o = is_y ? yvec<T>(d, kind) : xvec<T>(d, kind);
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) o[i] = (T)v;
 }
 
@@ -781,8 +645,8 @@ __global__ __launch_bounds__(VEC_NT) void k_copy(Tables tb, int is_y, int dst, i
     const VecTile tl = is_y ? tb.yt[blockIdx.x] : tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
-    T* o = is_y ? yvec<T>(d, dst) : xvec<T>(d, dst);
-    const T* s = is_y ? yvec<T>(d, src) : xvec<T>(d, src);
+    gptr<T> o = is_y ? yvec<T>(d, dst) : xvec<T>(d, dst);
+    gptr<const T> s = is_y ? yvec<T>(d, src) : xvec<T>(d, src);
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) o[i] = s[i];
 }
 
@@ -790,10 +654,10 @@ template <typename T>
 __global__ void k_extract(const InstDesc* insts, int inst, int what, int64_t off, int64_t len,
                           double* out) {
     const InstDesc d = insts[inst];
-    const double* sc = scal(d);
+    gptr<const double> sc = scal(d);
     const double status = sc[SC_STATUS];
     double scale = 1.0;
-    const T* v;
+    gptr<const T> v;
     if (what == 0 || what == 3) v = xvec<T>(d, XU);
     else if (what == 1 || what == 4) v = yvec<T>(d, YU);
     else v = yvec<T>(d, YV);
@@ -863,14 +727,19 @@ __global__ void k_set_scalar(const InstDesc* insts, int inst, int slot, double v
     if (threadIdx.x == 0 && blockIdx.x == 0) reinterpret_cast<double*>(insts[inst].base)[slot] = v;
 }
 
-__global__ void k_to_bf16(const float* src, uint16_t* dst, int64_t n) {
+DEVI uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);   // round to nearest even
+}
+
+__global__ void k_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t u = __float_as_uint(src[i]);
-        uint16_t h;
-        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) h = (uint16_t)((u >> 16) | 0x40u);
-        else h = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);   // round to nearest even
-        dst[i] = h;
+        const float x = src[i];
+        const uint16_t h = bf16_rne(x);
+        hi[i] = h;
+        lo[i] = bf16_rne(x - __uint_as_float((uint32_t)h << 16));
     }
 }
 
@@ -896,7 +765,10 @@ void launch_apply_init(int prec, const Tables& t, int adj, int out, int in, int 
 }
 void launch_conv(int prec, const Tables& t, const ConvLaunch& c, int adj, int out, int in,
                  double sigma, int gate, hipStream_t st) {
-    CGS_DISPATCH(prec, k_conv, c.ntiles, CONV_NT, st, t, c, adj, out, in, sigma, gate);
+    if (c.ntiles <= 0) return;
+    const size_t lds = conv_smem_bytes(prec, c.kc);
+    if (prec == 0) k_conv<double><<<c.ntiles, CONV_NT, lds, st>>>(t, c, adj, out, in, sigma, gate);
+    else k_conv<float><<<c.ntiles, CONV_NT, lds, st>>>(t, c, adj, out, in, sigma, gate);
 }
 void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int out, int in,
                  double sigma, int gate, hipStream_t st) {
@@ -906,13 +778,17 @@ void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h
                     double zeta, double rate, double floor_, int cg_max, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_init, t.nx_tiles, VEC_NT, st, t, z, r, p, q, h, have_q, zeta, rate,
                  floor_, cg_max, gate);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_INIT, gate, FinArgs{zeta, rate, floor_, cg_max, 0});
 }
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, gate);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_DOT, gate, FinArgs{0, 0, 0, 0, 0});
 }
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int cg_max,
-                      int gate, hipStream_t st) {
-    CGS_DISPATCH(prec, k_cg_update, t.nx_tiles, VEC_NT, st, t, z, r, p, q, cg_max, gate);
+                      int gate, int track, hipStream_t st) {
+    CGS_DISPATCH(prec, k_cg_update, t.nx_tiles + (track ? t.ny_tiles : 0), VEC_NT, st, t, z, r, p, q,
+                 cg_max, gate, track);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_UPDATE, gate, FinArgs{0, 0, 0, cg_max, 0});
 }
 void launch_cg_dir(int prec, const Tables& t, int r, int p, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_dir, t.nx_tiles, VEC_NT, st, t, r, p, gate);
@@ -920,26 +796,33 @@ void launch_cg_dir(int prec, const Tables& t, int r, int p, int gate, hipStream_
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_wy, t.ny_tiles, VEC_NT, st, t, gate);
 }
-void launch_tau_dots(int prec, const Tables& t, double alpha, hipStream_t st) {
-    CGS_DISPATCH(prec, k_tau_dots, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
+void launch_tau_dots(int prec, const Tables& t, double alpha, int form_zy, hipStream_t st) {
+    CGS_DISPATCH(prec, k_tau_dots, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha, form_zy);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_TAU, G_ADMM, FinArgs{alpha, 0, 0, 0, 0});
 }
 void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st) {
-    if (t.nseg > 0) CGS_DISPATCH(prec, k_soc_prep, t.ny_tiles, VEC_NT, st, t, alpha);
+    if (t.nseg > 0) {
+        CGS_DISPATCH(prec, k_soc_prep, t.ny_tiles, VEC_NT, st, t, alpha);
+        k_finalize_soc<<<t.nseg, VEC_NT, 0, st>>>(t);
+    }
 }
 void launch_project(int prec, const Tables& t, double alpha, hipStream_t st) {
     CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
 }
 void launch_resid(int prec, const Tables& t, double eps, int max_iters, hipStream_t st) {
     CGS_DISPATCH(prec, k_resid, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, eps, max_iters);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_RESID, G_CHECK, FinArgs{eps, 0, 0, max_iters, 0});
 }
 void launch_reset(int prec, const Tables& t, int only, hipStream_t st) {
     CGS_DISPATCH(prec, k_reset, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, only);
 }
 void launch_norms(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_norms, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, gate);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_NORMS, gate, FinArgs{0, 0, 0, 0, 0});
 }
 void launch_eta(int prec, const Tables& t, hipStream_t st) {
     CGS_DISPATCH(prec, k_eta, t.nx_tiles + t.ny_tiles, VEC_NT, st, t);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_ETA, G_SETUP, FinArgs{0, 0, 0, 0, 0});
 }
 void launch_fill(int prec, const Tables& t, int is_y, int kind, double v, int gate,
                  hipStream_t st) {
@@ -982,8 +865,8 @@ void launch_gather_scalars(const InstDesc* insts, int ninst, double* out, hipStr
 void launch_set_scalar(const InstDesc* insts, int inst, int slot, double v, hipStream_t st) {
     k_set_scalar<<<1, 64, 0, st>>>(insts, inst, slot, v);
 }
-void launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t st) {
-    if (n > 0) k_to_bf16<<<flat_grid(n, 256), 256, 0, st>>>(src, dst, n);
+void launch_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st) {
+    if (n > 0) k_to_bf16<<<flat_grid(n, 256), 256, 0, st>>>(src, hi, lo, n);
 }
 
 }  // namespace cgs

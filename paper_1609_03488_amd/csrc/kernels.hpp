@@ -14,7 +14,10 @@ struct ConvLaunch {
     const ConvTile* tiles;
     const ConvBlock* blocks;
     int ntiles;
+    int kc;          // taps per LDS staging pass: min(max kpad of the launch, CONV_KC_MAX)
 };
+// dynamic LDS bytes of the convolution kernel for a staging pass of kc taps
+size_t conv_smem_bytes(int prec, int kc);
 struct DenseLaunch {
     const DenseTile* tiles;
     const DenseBlock* blocks;
@@ -28,6 +31,10 @@ void launch_apply_init(int prec, const Tables& t, int adj, int out, int in, int 
 // out += sigma * scale * conv(in) for every conv tile (adj selects A or A^T).
 void launch_conv(int prec, const Tables& t, const ConvLaunch& c, int adj, int out, int in,
                  double sigma, int gate, hipStream_t st);
+// FP32 only: the same convolution tiles on the matrix cores (conv_mfma.hip)
+void launch_conv_mfma(const Tables& t, const ConvLaunch& c, int adj, int out, int in, double sigma,
+                      int gate, hipStream_t st);
+size_t conv_mfma_smem_bytes(int kc);
 // out += sigma * scale * a (or a^T) * in for every dense tile.
 void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int out, int in,
                  double sigma, int gate, hipStream_t st);
@@ -40,8 +47,9 @@ void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h
 // alpha = rr / <p, q>
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int gate, hipStream_t st);
 // z += alpha p; r -= alpha q; rr' = ||r||^2; beta = rr'/rr; stop test
+// track = 1: also K z += alpha q and A z += alpha (A p) (carried products)
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int cg_max,
-                      int gate, hipStream_t st);
+                      int gate, int track, hipStream_t st);
 // p = r + beta p
 void launch_cg_dir(int prec, const Tables& t, int r, int p, int gate, hipStream_t st);
 
@@ -49,7 +57,8 @@ void launch_cg_dir(int prec, const Tables& t, int r, int p, int gate, hipStream_
 // w_y = u_y + v_s
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st);
 // u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta, then tau, kappa updates
-void launch_tau_dots(int prec, const Tables& t, double alpha, hipStream_t st);
+// form_zy = 1: z_y = w_y + (carried A z) is formed in the same pass
+void launch_tau_dots(int prec, const Tables& t, double alpha, int form_zy, hipStream_t st);
 // head value and tail sum of squares of (u_bar_y - v_s) per second-order cone
 void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st);
 // relaxation, projection onto K, dual update of every X/Y entry
@@ -84,7 +93,39 @@ void launch_cast_back(int prec, const void* src, double* dst, int64_t n, hipStre
 // out[i * NSC + j] = scalar j of instance i
 void launch_gather_scalars(const InstDesc* insts, int ninst, double* out, hipStream_t st);
 void launch_set_scalar(const InstDesc* insts, int inst, int slot, double v, hipStream_t st);
-// BF16 copies (round to nearest even) of a working-precision FP32 matrix
-void launch_to_bf16(const float* src, uint16_t* dst, int64_t n, hipStream_t st);
+// BF16 copies (round to nearest even) of a working-precision FP32 matrix: hi =
+// bf16(x), lo = bf16(x - hi)
+void launch_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st);
+
+// ---- fused small-instance steps (fused.hip): one workgroup per instance runs
+// nsteps ADMM steps and, with check, the termination test and the exact
+// recomputation of the carried warm-start products.
+struct FusedArgs {
+    int nsteps;
+    int check;
+    double alpha, eps, zeta, rate, floor_;
+    int cg_max;
+    int max_iters;
+    int kc;          // taps per LDS staging pass (as ConvLaunch::kc)
+};
+size_t fused_smem_bytes(int prec, int kc);
+void launch_fused(int prec, const Tables& t, const FusedArgs& fa, hipStream_t st);
+
+// ---- batched dense applies as BF16 MFMA GEMMs (gemm.hip)
+struct GemmPlan {
+    int mpad;               // instances padded to the 64-row M tile
+    int ntiles;             // 128-column N tiles
+    int ksteps_per_split;   // 16-wide K steps per split
+    int nsplit;             // K splits (partials reduced in fixed order)
+    int64_t npad;
+};
+GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst);
+size_t gemm_part_bytes(const GemmPlan& g);
+// out_b += sigma * scale * W x_b for every instance b (W = A, or A^T when adj),
+// W in BF16 (plus refinement products when corr); panel_hi/lo hold
+// mpad x kpad BF16 values, part the split-K partials.
+void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
+                       double sigma, int gate, int corr, uint16_t* panel_hi, uint16_t* panel_lo,
+                       float* part, hipStream_t st);
 
 }  // namespace cgs

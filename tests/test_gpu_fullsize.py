@@ -1,0 +1,121 @@
+"""GPU checks at the benchmark sizes, in the launch configuration bench.py uses.
+
+Exact optima come from tests/golden/reference_objectives.json (written by
+tests/golden/make_reference.py from the FP64 oracle only).  The n = 2^20
+deconvolution has no affordable exact optimum, so it is checked through
+properties that hold at any size: the KKT residuals of the returned point
+recomputed in FP64 on the host, and the objective bound ||noise|| (x_true is
+feasible).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_1609_03488_amd")
+REF = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "reference_objectives.json")))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def test_deconv_n1M_k1025_fp32():
+    import torch
+    cfg = w.workload("deconv_n1M_k1025")
+    _say(cfg["name"])
+    d = w.make_deconv(cfg)
+    pr = P.deconv_problem(d["c"], d["b"])
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10)
+    s = P.Solver(pr.op, pr.l, pr.q, st, stream=torch.cuda.Stream())
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, y, sl = s.solution(0)
+    prog = o.deconv_program(d["c"], d["b"])
+    rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+    assert max(rp, rd, gap) <= 1.05e-4, (rp, rd, gap)
+    f = o.deconv_objective(d["c"], d["b"], x[:cfg["n"]])
+    noise = np.linalg.norm(d["b"] - np.convolve(d["c"], d["x_true"]))
+    assert f <= noise * (1 + 1e-4), (f, noise)
+    # dual side: y in K (cone membership of the returned dual point)
+    assert o.in_cone(y, prog.l, prog.q, 1e-6 * (1 + np.abs(y).max()))
+
+
+def test_deconv_n1000_k101_fp64_against_exact_nnls():
+    cfg = w.workload("deconv_n1000_k101")
+    _say(cfg["name"])
+    d = w.make_deconv(cfg)
+    pr = P.deconv_problem(d["c"], d["b"])
+    # 1e-6 is out of reach of the method in 1e5 iterations; check 1e-4
+    st = P.Settings.make(precision=P.FP64, eps=1e-4, check_every=10)
+    s = P.Solver(pr.op, pr.l, pr.q, st)
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, y, sl = s.solution(0)
+    prog = o.deconv_program(d["c"], d["b"])
+    rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+    assert max(rp, rd, gap) <= 1.05e-4
+    f = o.deconv_objective(d["c"], d["b"], x[:1000])
+    fref = o.scs_solve(prog, eps=1e-4, check_every=10)
+    fo = o.deconv_objective(d["c"], d["b"], fref.x[:1000])
+    assert abs(f - fo) / fo <= 1e-4, (f, fo)
+    exact = REF[cfg["name"]]["objective"]
+    assert exact <= f and (f - exact) / exact < 5e-3
+
+
+def test_lasso_5000x10000_fp32_against_exact():
+    import torch
+    cfg = w.workload("lasso_5000x10000")
+    _say(cfg["name"])
+    d = w.make_lasso(cfg)
+    pr = P.lasso_problem(d["A"], d["b"], d["lam"])
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10)
+    s = P.Solver(pr.op, pr.l, pr.q, st, stream=torch.cuda.Stream())
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, y, sl = s.solution(0)
+    prog = o.lasso_program(d["A"], d["b"], d["lam"])
+    rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+    assert max(rp, rd, gap) <= 1.05e-4, (rp, rd, gap)
+    f = o.lasso_objective(d["A"], d["b"], float(d["lam"]), x[:cfg["n"]])
+    exact = REF[cfg["name"]]["objective"]
+    assert abs(f - exact) / exact <= 1e-4, (f, exact)
+
+
+def test_lasso_batch64_bf16_against_exact():
+    import torch
+    cfg = w.workload("lasso_batch64_2000x8000")
+    _say(cfg["name"])
+    d = w.make_lasso_batch(cfg)
+    B = cfg["batch"]
+    prs = [P.lasso_problem(d["A"], d["b"][i], d["lam"][i]) for i in range(B)]
+    st = P.Settings.make(precision=P.BF16, eps=cfg["eps"], check_every=10)
+    s = P.Solver(prs[0].op, prs[0].l, prs[0].q, st, batch=B, stream=torch.cuda.Stream())
+    for i, pr in enumerate(prs):
+        s.set_data(i, pr.b, pr.c)
+    infos = s.solve()
+    assert all(inf["status"] == P.SOLVED for inf in infos), [inf["status"] for inf in infos]
+    for key, ref in REF[cfg["name"]].items():
+        i = int(key)
+        x, y, sl = s.solution(i)
+        prog = o.lasso_program(d["A"], d["b"][i], d["lam"][i])
+        rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+        assert max(rp, rd, gap) <= 1.5e-4, (i, rp, rd, gap)
+        f = o.lasso_objective(d["A"], d["b"][i], d["lam"][i], x[:cfg["n"]])
+        assert abs(f - ref["objective"]) / ref["objective"] <= 1e-4, (i, f, ref["objective"])
