@@ -225,6 +225,13 @@ int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, 
  * application p + A^T A p.  *avg_ms receives the mean time per launch (per
  * operator block, for 0-3); CGS_ENOTFOUND if the operator has no such block. */
 int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* avg_ms);
+/* Autotuner: times the candidate kernel configurations on the solver's own
+ * operator and vectors (HIP events, `reps` launches each) and keeps the
+ * fastest -- the convolution engine for FP32 (vector ALU or matrix cores) and
+ * the split-K width of the batched BF16 GEMM.  choice[2] (nullable) receives
+ * {conv_mfma (or -1), GEMM workgroup target (or -1)}.  Results do not change:
+ * only how the same products are computed. */
+int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice);
 void cgs_solver_destroy(cgs_solver* s);
 
 /* ---------------------------------------------------------------- server

@@ -92,6 +92,7 @@ _SIGS = {
     "cgs_solver_normal_solve": (C.c_int, [_P, _DP, _DP, _DP, _D, C.c_int32,
                                           C.POINTER(C.c_int32)]),
     "cgs_solver_kernel_time": (C.c_int, [_P, C.c_int32, C.c_int32, _DP]),
+    "cgs_solver_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "cgs_solver_destroy": (None, [_P]),
     "cgs_server_request_bytes": (C.c_int, [_P, _I64, _I64P, _I64, C.c_int32,
                                            C.POINTER(C.c_size_t)]),
@@ -238,6 +239,12 @@ class Solver:
         ms = C.c_double()
         _check(lib().cgs_solver_kernel_time(self._h, int(kernel), int(reps), C.byref(ms)))
         return float(ms.value)
+
+    def autotune(self, reps: int = 10) -> dict:
+        """Pick the fastest convolution engine / GEMM split for this operator."""
+        ch = (C.c_int32 * 2)()
+        _check(lib().cgs_solver_autotune(self._h, int(reps), ch))
+        return {"conv_mfma": int(ch[0]), "gemm_target_wgs": int(ch[1])}
 
     def solve(self) -> List[dict]:
         infos = (Info * self.batch)()

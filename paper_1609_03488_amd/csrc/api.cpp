@@ -70,9 +70,11 @@ int solver_layout(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, con
         for (const cgs::DenseBlock& db : shape.dense) {
             for (int adj = 0; adj < 2; ++adj) {
                 const int64_t N = adj ? db.cols : db.rows, kpad = adj ? db.ldt : db.ld;
-                const cgs::GemmPlan g = cgs::gemm_plan(N, kpad, (int)batch);
-                L->panel = std::max(L->panel, cgs::align256((size_t)g.mpad * kpad * 2));
-                L->part = std::max(L->part, cgs::align256(cgs::gemm_part_bytes(g)));
+                for (int target = 128; target <= cgs::GEMM_TARGET_MAX; target *= 2) {
+                    const cgs::GemmPlan g = cgs::gemm_plan(N, kpad, (int)batch, target);
+                    L->panel = std::max(L->panel, cgs::align256((size_t)g.mpad * kpad * 2));
+                    L->part = std::max(L->part, cgs::align256(cgs::gemm_part_bytes(g)));
+                }
             }
         }
     }
@@ -338,7 +340,8 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
                 for (const cgs::DenseBlock& db : s->opdev.dense)
                     cgs::launch_gemm_apply(e.inst_dev, e.T.ninst, db, adj, adj ? cgs::XT : cgs::YT,
                                            adj ? cgs::YU : cgs::XU, 1.0, cgs::G_ALL, e.gemm_corr,
-                                           e.panel_hi, e.panel_lo, e.gemm_part, e.stream), ++launches;
+                                           e.panel_hi, e.panel_lo, e.gemm_part, e.gemm_target, e.stream),
+                        ++launches;
             } else {
                 for (const auto& d : dl)
                     cgs::launch_gemv(e.prec, e.T, d, adj, adj ? cgs::XT : cgs::YT, adj ? cgs::YU : cgs::XU,
@@ -358,6 +361,49 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
     (void)hipEventDestroy(b);
     CGS_HIP(hipGetLastError());
     *avg_ms = (double)ms / launches;
+    return CGS_OK;
+}
+
+int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice) {
+    if (!s) return fail(CGS_EINVAL, "solver is null");
+    if (reps < 1) return fail(CGS_EINVAL, "reps must be >= 1");
+    cgs::Engine& e = s->eng;
+    int32_t out[2] = {-1, -1};
+    double best = 0.0;
+    if (!e.cf.empty() && e.prec == 1) {
+        // convolution engine: vector ALU or matrix cores, A and A^T together
+        double t[2];
+        for (int m = 0; m < 2; ++m) {
+            e.st.conv_mfma = m;
+            double a = 0.0, b = 0.0;
+            CGS_TRY(cgs_solver_kernel_time(s, 0, reps, &a));
+            CGS_TRY(cgs_solver_kernel_time(s, 1, reps, &b));
+            t[m] = a + b;
+        }
+        e.st.conv_mfma = t[1] < t[0] ? 1 : 0;
+        out[0] = e.st.conv_mfma;
+    }
+    if (e.use_gemm) {
+        // split-K of the batched GEMM: workgroups aimed for
+        int bt = e.gemm_target;
+        for (int target = 128; target <= cgs::GEMM_TARGET_MAX; target *= 2) {
+            e.gemm_target = target;
+            double a = 0.0, b = 0.0;
+            CGS_TRY(cgs_solver_kernel_time(s, 2, reps, &a));
+            CGS_TRY(cgs_solver_kernel_time(s, 3, reps, &b));
+            if (target == 128 || a + b < best) {
+                best = a + b;
+                bt = target;
+            }
+        }
+        e.gemm_target = bt;
+        out[1] = bt;
+    }
+    e.drop_graph();
+    if (choice) {
+        choice[0] = out[0];
+        choice[1] = out[1];
+    }
     return CGS_OK;
 }
 

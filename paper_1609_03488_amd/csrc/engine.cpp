@@ -431,7 +431,7 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
         // every instance shares the dense blocks: one MFMA GEMM per block
         for (const DenseBlock& db : recs[0].op->dense)
             launch_gemm_apply(inst_dev, T.ninst, db, adj, out, in, sigma, gate, gemm_corr, panel_hi,
-                              panel_lo, gemm_part, stream);
+                              panel_lo, gemm_part, gemm_target, stream);
     } else {
         for (const auto& d : adj ? da : df) launch_gemv(prec, T, d, adj, out, in, sigma, gate, stream);
     }

@@ -141,6 +141,7 @@ class Engine {
     uint16_t* panel_hi = nullptr;
     uint16_t* panel_lo = nullptr;
     float* gemm_part = nullptr;
+    int gemm_target = 512;       // GEMM workgroups aimed for (autotuned)
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -159,14 +159,14 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const InstDesc* insts, int 
 }
 
 // ---------------------------------------------------------------- launchers
-GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst) {
+GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst, int target_wgs) {
     GemmPlan g{};
     g.mpad = (int)((ninst + GEMM_TM - 1) / GEMM_TM * GEMM_TM);
     g.ntiles = (int)((N + GEMM_TN - 1) / GEMM_TN);
     g.npad = (int64_t)g.ntiles * GEMM_TN;
     const int64_t ksteps = kpad / 16;
     const int mtiles = g.mpad / GEMM_TM;
-    int64_t want = 512 / ((int64_t)g.ntiles * mtiles);
+    int64_t want = (int64_t)target_wgs / ((int64_t)g.ntiles * mtiles);
     if (want < 1) want = 1;
     if (want > ksteps) want = ksteps;
     if (want > 64) want = 64;
@@ -179,7 +179,7 @@ size_t gemm_part_bytes(const GemmPlan& g) { return (size_t)g.nsplit * g.mpad * g
 
 void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
                        double sigma, int gate, int corr, uint16_t* panel_hi, uint16_t* panel_lo,
-                       float* part, hipStream_t st) {
+                       float* part, int target_wgs, hipStream_t st) {
     const int64_t N = adj ? db.cols : db.rows;        // outputs
     const int64_t K = adj ? db.rows : db.cols;        // inputs
     const int64_t kpad = adj ? db.ldt : db.ld;
@@ -187,7 +187,7 @@ void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, i
     const uint16_t* w_lo = (const uint16_t*)(adj ? db.at16lo : db.a16lo);
     const int64_t off_in = adj ? db.row0 : db.col0;
     const int64_t off_out = adj ? db.col0 : db.row0;
-    const GemmPlan g = gemm_plan(N, kpad, ninst);
+    const GemmPlan g = gemm_plan(N, kpad, ninst, target_wgs);
     dim3 pg((unsigned)((kpad + 255) / 256), (unsigned)g.mpad);
     k_gemm_pack<<<pg, 256, 0, st>>>(insts, ninst, adj, in, off_in, K, kpad, g.mpad, panel_hi, panel_lo);
     dim3 gg((unsigned)g.ntiles, (unsigned)g.nsplit, (unsigned)(g.mpad / GEMM_TM));

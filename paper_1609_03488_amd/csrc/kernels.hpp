@@ -119,13 +119,15 @@ struct GemmPlan {
     int nsplit;             // K splits (partials reduced in fixed order)
     int64_t npad;
 };
-GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst);
+// target_wgs: workgroups to aim for (K splits = target / (N tiles x M tiles), >= 1, <= 64)
+GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst, int target_wgs);
+constexpr int GEMM_TARGET_MAX = 1024;   // largest target the autotuner tries (sizes the partials)
 size_t gemm_part_bytes(const GemmPlan& g);
 // out_b += sigma * scale * W x_b for every instance b (W = A, or A^T when adj),
 // W in BF16 (plus refinement products when corr); panel_hi/lo hold
 // mpad x kpad BF16 values, part the split-K partials.
 void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
                        double sigma, int gate, int corr, uint16_t* panel_hi, uint16_t* panel_lo,
-                       float* part, hipStream_t st);
+                       float* part, int target_wgs, hipStream_t st);
 
 }  // namespace cgs

@@ -404,3 +404,29 @@ def test_bf16_batch_solve_matches_oracle():
         ref = o.scs_solve(progs[i], eps=1e-4, check_every=10)
         f, fr = _objective(progs[i], x), _objective(progs[i], ref.x)
         assert abs(f - fr) / abs(fr) <= 1e-4, (i, f, fr)
+
+
+# ----------------------------------------------------------------- autotuner
+
+def test_autotune_keeps_results_within_bounds():
+    """The autotuner only picks how the same products are computed: after it,
+    the FP32 convolution applies and the BF16 GEMM applies stay inside the
+    error bounds of the apply tests above."""
+    name, pr, prog = CASES[1]
+    _say("autotune conv", name)
+    s = _solver(pr, P.FP32)
+    ch = s.autotune(reps=3)
+    assert ch["conv_mfma"] in (0, 1) and ch["gemm_target_wgs"] == -1
+    rng = np.random.default_rng(5)
+    z = rng.standard_normal(prog.n)
+    u, K = 2.0 ** -24, prog.data["k"] + 4
+    assert np.all(np.abs(s.apply(z) - prog.A(z)) <= (K + 4) * u * _abs_bound(prog, z, False))
+    _say("autotune gemm")
+    A, prs, progs = _lasso_batch(300, 700, 37, 41)
+    s = _solver(prs[0], P.BF16, batch=37)
+    ch = s.autotune(reps=3)
+    assert ch["conv_mfma"] == -1 and ch["gemm_target_wgs"] in (128, 256, 512, 1024)
+    y = rng.standard_normal(progs[0].m)
+    tol = 2.0 ** -8 + 700 * 2.0 ** -24
+    assert np.all(np.abs(s.apply(y, transpose=True) - progs[0].AT(y))
+                  <= tol * _abs_bound(progs[0], y, True) + 1e-30)
