@@ -13,6 +13,8 @@ What it computes (plain, slow, obviously correct, float64 throughout):
   second-order cones, and the matrix ``I + A^T A`` factored directly (dense
   Cholesky, or banded Cholesky for a convolution block).
 * ``cones``    -- closed-form Euclidean projections onto those cones.
+* ``equil``    -- the diagonal equilibration the iteration runs on (a reading:
+  the paper leaves preconditioning open).
 * ``scs``      -- the homogeneous self-dual embedding ADMM iteration the paper
   runs ("SCS", Sections II-D and V-B), with the linear-subspace step solved
   exactly through the factorisation instead of by conjugate gradients.
@@ -24,12 +26,14 @@ silent the reading taken is stated in the function's docstring.
 """
 from .cones import proj_nonneg, proj_soc, proj_cone, in_cone
 from .program import ConeProgram, deconv_program, lasso_program, dense_program
-from .scs import scs_solve, ScsResult, hsde_subspace_step
+from .equil import Scaling, equilibrate, scaled_program
+from .scs import scs_solve, ScsResult, hsde_subspace_step, prepare
 from .polish import polish_deconv, polish_lasso, deconv_objective, lasso_objective
 
 __all__ = [
     "proj_nonneg", "proj_soc", "proj_cone", "in_cone",
     "ConeProgram", "deconv_program", "lasso_program", "dense_program",
-    "scs_solve", "ScsResult", "hsde_subspace_step",
+    "Scaling", "equilibrate", "scaled_program",
+    "scs_solve", "ScsResult", "hsde_subspace_step", "prepare",
     "polish_deconv", "polish_lasso", "deconv_objective", "lasso_objective",
 ]

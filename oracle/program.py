@@ -35,7 +35,9 @@ class ConeProgram:
 
     def __init__(self, n: int, m: int, b: np.ndarray, c: np.ndarray, l: int, q: Sequence[int],
                  apply: Callable, apply_T: Callable, explicit: Callable,
-                 factor: Callable, family: str, data: Optional[dict] = None):
+                 factor: Callable, family: str, data: Optional[dict] = None,
+                 blocks: Sequence[tuple] = (), apply_sq: Optional[Callable] = None,
+                 scaled_factor: Optional[Callable] = None):
         self.n, self.m = int(n), int(m)
         self.b = np.asarray(b, dtype=np.float64)
         self.c = np.asarray(c, dtype=np.float64)
@@ -45,6 +47,11 @@ class ConeProgram:
         self._explicit, self._factor = explicit, factor
         self.family = family
         self.data = data or {}
+        # (row0, rows, col0, cols) of every nonzero block of A, the product of
+        # A's entrywise square with a vector, and the factorisation of
+        # I + (D A E)^T (D A E) for diagonal scalings constant on the blocks
+        self.blocks = [tuple(int(v) for v in bl) for bl in blocks]
+        self._apply_sq, self._scaled_factor = apply_sq, scaled_factor
         if self.b.shape != (self.m,) or self.c.shape != (self.n,):
             raise ValueError("b/c shape mismatch")
         if self.l + sum(self.q) != self.m:
@@ -63,6 +70,21 @@ class ConeProgram:
     def factor(self) -> Factor:
         return self._factor()
 
+    def A_sq(self, x: np.ndarray) -> np.ndarray:
+        """``(A o A) x``: ``A`` with every entry squared, applied to ``x``."""
+        return self._apply_sq(np.asarray(x, dtype=np.float64))
+
+    def scaled_factor(self, D: np.ndarray, E: np.ndarray) -> Factor:
+        """Factorisation of ``I + (D A E)^T (D A E)`` for diagonal ``D`` (rows) and
+        ``E`` (columns) that are constant on each block of ``A``."""
+        return self._scaled_factor(np.asarray(D, dtype=np.float64), np.asarray(E, dtype=np.float64))
+
+
+def _require_constant(v: np.ndarray, ranges) -> None:
+    for lo, hi in ranges:
+        if hi > lo and np.any(v[lo:hi] != v[lo]):
+            raise ValueError("scaling is not constant on a block of the operator")
+
 
 def _dense_factor(M: np.ndarray) -> Factor:
     """Cholesky of the SPD matrix ``M``."""
@@ -79,8 +101,15 @@ def dense_program(A: np.ndarray, b: np.ndarray, c: np.ndarray, l: int,
     def factor():
         return _dense_factor(np.eye(n) + A.T @ A)
 
+    def scaled_factor(D, E):
+        As = D[:, None] * A * E[None, :]
+        return _dense_factor(np.eye(n) + As.T @ As)
+
+    A2 = A * A
     return ConeProgram(n, m, b, c, l, q, lambda x: A @ x, lambda y: A.T @ y,
-                       lambda: A.copy(), factor, "dense", {"A": A})
+                       lambda: A.copy(), factor, "dense", {"A": A},
+                       blocks=[(0, m, 0, n)], apply_sq=lambda x: A2 @ x,
+                       scaled_factor=scaled_factor)
 
 
 def conv_matrix(c: np.ndarray, n: int) -> np.ndarray:
@@ -143,24 +172,40 @@ def deconv_program(c: np.ndarray, b_obs: np.ndarray) -> ConeProgram:
         A[n + 1:, :n] = -conv_matrix(c, n)
         return A
 
-    def factor():
-        r = autocorrelation(c)
+    def banded(p, q, r):
+        # I + A^T A for A = [[-p I, 0], [0, -q], [-r C, 0]]:
+        # blockdiag((1 + p^2) I + r^2 C^T C, 1 + q^2)
+        ac = autocorrelation(c)
         kd = min(k - 1, n - 1)
         ab = np.zeros((kd + 1, n))          # upper banded storage
         for d in range(kd + 1):
-            ab[kd - d, d:] = r[d]
-        ab[kd, :] += 2.0
+            ab[kd - d, d:] = r * r * ac[d]
+        ab[kd, :] += 1.0 + p * p
         cb = sla.cholesky_banded(ab, lower=False, check_finite=False)
+        tt = 1.0 + q * q
 
         def solve(rhs):
             out = np.empty(nv)
             out[:n] = sla.cho_solve_banded((cb, False), rhs[:n], check_finite=False)
-            out[n] = rhs[n] / 2.0
+            out[n] = rhs[n] / tt
             return out
         return Factor(solve, "banded")
 
-    return ConeProgram(nv, m, b, cc, n, [n + k], apply, apply_T, explicit, factor,
-                       "deconv", {"c": c, "b_obs": b_obs, "n": n, "k": k})
+    def scaled_factor(D, E):
+        _require_constant(D, [(0, n), (n, m)])
+        _require_constant(E, [(0, n), (n, nv)])
+        return banded(D[0] * E[0], D[n] * E[n], D[n + 1] * E[0])
+
+    c2 = c * c
+
+    def apply_sq(z):
+        return np.concatenate([z[:n], [z[n]], np.convolve(c2, z[:n])])
+
+    return ConeProgram(nv, m, b, cc, n, [n + k], apply, apply_T, explicit,
+                       lambda: banded(1.0, 1.0, 1.0), "deconv",
+                       {"c": c, "b_obs": b_obs, "n": n, "k": k},
+                       blocks=[(0, n, 0, n), (n, 1, n, 1), (n + 1, n + k - 1, 0, n)],
+                       apply_sq=apply_sq, scaled_factor=scaled_factor)
 
 
 def lasso_program(A: np.ndarray, b_obs: np.ndarray, lam: float) -> ConeProgram:
@@ -207,15 +252,41 @@ def lasso_program(A: np.ndarray, b_obs: np.ndarray, lam: float) -> ConeProgram:
         Ac[m - 1, 2 * n0] = -1.0
         return Ac
 
-    def factor():
-        cf = sla.cho_factor(3.0 * np.eye(n0) + 4.0 * (A.T @ A), lower=False, check_finite=False)
+    def blockdiag(dx, dt, du, r):
+        # I + A^T A when the x, t and u columns carry the row-group weights
+        # dx = sum of squared x coefficients in the nonnegative rows (and dt, du
+        # likewise) and the dense block is -r A: blockdiag((1 + dx) I + r^2 A^T A,
+        # (1 + dt) I, 1 + du); the x-t cross terms of the rows t - x and t + x cancel.
+        cf = sla.cho_factor((1.0 + dx) * np.eye(n0) + r * r * (A.T @ A), lower=False,
+                            check_finite=False)
 
         def solve(rhs):
             out = np.empty(nv)
             out[:n0] = sla.cho_solve(cf, rhs[:n0], check_finite=False)
-            out[n0:] = rhs[n0:] / 3.0
+            out[n0:2 * n0] = rhs[n0:2 * n0] / (1.0 + dt)
+            out[2 * n0] = rhs[2 * n0] / (1.0 + du)
             return out
         return Factor(solve, "lasso-blockdiag")
 
-    return ConeProgram(nv, m, b, cc, 2 * n0, [m0 + 2], apply, apply_T, explicit, factor,
-                       "lasso", {"A": A, "b_obs": b_obs, "lam": float(lam), "n": n0, "m": m0})
+    def scaled_factor(D, E):
+        _require_constant(D, [(0, n0), (n0, 2 * n0), (2 * n0, m)])
+        _require_constant(E, [(0, n0), (n0, 2 * n0), (2 * n0, nv)])
+        d1, d2, d3 = D[0], D[n0], D[2 * n0]
+        ex, et, eu = E[0], E[n0], E[2 * n0]
+        if d1 != d2:
+            raise ValueError("rows t - x and t + x must carry the same scale")
+        return blockdiag(2.0 * (d1 * ex) ** 2, 2.0 * (d1 * et) ** 2, 2.0 * (d3 * eu) ** 2,
+                         2.0 * d3 * ex)
+
+    A2 = A * A
+
+    def apply_sq(z):
+        x, t, u = z[:n0], z[n0:2 * n0], z[2 * n0]
+        return np.concatenate([x + t, x + t, [u], 4.0 * (A2 @ x), [u]])
+
+    return ConeProgram(nv, m, b, cc, 2 * n0, [m0 + 2], apply, apply_T, explicit,
+                       lambda: blockdiag(2.0, 2.0, 2.0, 2.0), "lasso",
+                       {"A": A, "b_obs": b_obs, "lam": float(lam), "n": n0, "m": m0},
+                       blocks=[(0, n0, 0, n0), (0, n0, n0, n0), (n0, n0, 0, n0), (n0, n0, n0, n0),
+                               (2 * n0, 1, 2 * n0, 1), (i_mid, m0, 0, n0), (m - 1, 1, 2 * n0, 1)],
+                       apply_sq=apply_sq, scaled_factor=scaled_factor)

@@ -28,10 +28,12 @@ Iteration (relaxation ``alpha``)::
 ``z = M^{-1} w_xy`` (``z_x = K^{-1}(w_x - A^T w_y)``, ``z_y = w_y + A z_x``),
 ``u~_tau = (w_tau + c^T z_x + b^T z_y) / eta``, ``u~_xy = z - u~_tau g``.
 
-Readings where the paper is silent: unscaled data (no equilibration),
-``alpha = 1.5``, start ``u = v = (0, 0, 1)``; ``v_x`` stays 0 and is not stored
-(the ``y``-block of ``v`` is ``s``).  Termination uses the relative 2-norm
-criteria ``res_pri = ||A x + s - b|| / (1 + ||b||)``,
+Readings where the paper is silent: the iteration runs on the block-constant
+equilibrated data of ``oracle.equil`` (``normalize=True``, the default) or on
+the data as given, ``alpha = 1.5``, start ``u = v = (0, 0, 1)``; ``v_x`` stays
+0 and is not stored (the ``y``-block of ``v`` is ``s``).  Termination, on the
+unscaled point, uses the relative 2-norm criteria
+``res_pri = ||A x + s - b|| / (1 + ||b||)``,
 ``res_dual = ||A^T y + c|| / (1 + ||c||)``,
 ``gap = |c^T x + b^T y| / (1 + |c^T x| + |b^T y|)`` at ``(x, y, s) = (u_x, u_y,
 v_s)/tau``; when ``tau < kappa`` the infeasibility / unboundedness certificates
@@ -47,6 +49,7 @@ from typing import Callable, Optional
 import numpy as np
 
 from .cones import proj_cone
+from .equil import Scaling, equilibrate, identity_scaling, scaled_program
 from .program import ConeProgram, Factor
 
 
@@ -66,7 +69,8 @@ class ScsResult:
     gap: float
     setup_s: float
     solve_s: float
-    u: Optional[tuple] = None   # final (u_x, u_y, tau, v_s, kappa)
+    u: Optional[tuple] = None   # final (u_x, u_y, tau, v_s, kappa) of the scaled problem
+    scaling: Optional[Scaling] = None
 
 
 def embedding_vector(prog: ConeProgram, fac: Factor):
@@ -96,17 +100,29 @@ def residuals(prog: ConeProgram, ux, uy, tau, vs):
     return rp, rd, gap, cx, -by
 
 
+def prepare(prog: ConeProgram, normalize: bool = True):
+    """``(working program, scaling)``: the equilibrated program, or ``prog`` itself."""
+    if normalize:
+        scl = equilibrate(prog)
+        return scaled_program(prog, scl), scl
+    return prog, identity_scaling(prog)
+
+
 def scs_solve(prog: ConeProgram, eps: float = 1e-8, alpha: float = 1.5,
               max_iters: int = 100_000, check_every: int = 1,
               fac: Optional[Factor] = None, warm: Optional[tuple] = None,
               callback: Optional[Callable] = None,
-              time_limit_s: Optional[float] = None) -> ScsResult:
+              time_limit_s: Optional[float] = None, normalize: bool = True) -> ScsResult:
     """Run the HSDE ADMM iteration to the relative tolerance ``eps``.
 
-    ``warm`` = ``(u_x, u_y, tau, v_s, kappa)`` resumes from a saved state.
-    ``callback(it, ux, uy, tau, vs, kappa)`` sees every iterate.
+    ``fac`` factors ``I + A^T A`` of the working (scaled) program.
+    ``warm`` = ``(u_x, u_y, tau, v_s, kappa)`` resumes from a saved state and
+    ``callback(it, ux, uy, tau, vs, kappa)`` sees every iterate, both in the
+    variables of the working program.
     """
     t0 = time.perf_counter()
+    orig = prog
+    prog, scl = prepare(orig, normalize)
     if fac is None:
         fac = prog.factor()
     gx, gy, eta = embedding_vector(prog, fac)
@@ -140,30 +156,33 @@ def scs_solve(prog: ConeProgram, eps: float = 1e-8, alpha: float = 1.5,
         if callback is not None:
             callback(it, ux, uy, tau, vs, kappa)
         if it % check_every == 0 or it == max_iters:
+            # the point of the original problem (a positive multiple of it for rays)
+            rx, ry, rs = scl.unscale(ux, uy, 1.0, vs)
             if tau > 0.0:
-                rp, rd, gap, pobj, dobj = residuals(prog, ux, uy, tau, vs)
+                rp, rd, gap, pobj, dobj = residuals(orig, rx, ry, tau, rs)
                 if rp <= eps and rd <= eps and gap <= eps:
                     status = "solved"
                     break
             if tau < kappa:
-                bty = float(prog.b @ uy)
-                if bty < 0.0 and np.linalg.norm(prog.AT(uy)) <= eps * (-bty):
+                bty = float(orig.b @ ry)
+                if bty < 0.0 and np.linalg.norm(orig.AT(ry)) <= eps * (-bty):
                     status = "infeasible"
                     break
-                ctx = float(prog.c @ ux)
-                if ctx < 0.0 and np.linalg.norm(prog.A(ux) + vs) <= eps * (-ctx):
+                ctx = float(orig.c @ rx)
+                if ctx < 0.0 and np.linalg.norm(orig.A(rx) + rs) <= eps * (-ctx):
                     status = "unbounded"
                     break
             if time_limit_s is not None and time.perf_counter() - t1 > time_limit_s:
                 break
     t2 = time.perf_counter()
+    rx, ry, rs = scl.unscale(ux, uy, 1.0, vs)
     if status == "infeasible":
-        scale = -float(prog.b @ uy)
-        x, y, s = np.full(n, np.nan), uy / scale, np.full(m, np.nan)
+        scale = -float(orig.b @ ry)
+        x, y, s = np.full(n, np.nan), ry / scale, np.full(m, np.nan)
     elif status == "unbounded":
-        scale = -float(prog.c @ ux)
-        x, y, s = ux / scale, np.full(m, np.nan), vs / scale
+        scale = -float(orig.c @ rx)
+        x, y, s = rx / scale, np.full(m, np.nan), rs / scale
     else:
-        x, y, s = ux / tau, uy / tau, vs / tau
+        x, y, s = rx / tau, ry / tau, rs / tau
     return ScsResult(status, x, y, s, tau, kappa, it, pobj, dobj, rp, rd, gap,
-                     t1 - t0, t2 - t1, (ux, uy, tau, vs, kappa))
+                     t1 - t0, t2 - t1, (ux, uy, tau, vs, kappa), scl)

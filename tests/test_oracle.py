@@ -345,3 +345,108 @@ def test_deconv_small_workload_against_nnls_and_noise_bound():
     # a 1e-4 residual stop leaves the objective of this ill-conditioned blur
     # within a few 1e-3 of the optimum
     assert (f - ref["obj"]) / ref["obj"] < 5e-3
+
+
+# ----------------------------------------------------------------- equilibration
+
+def _small_programs():
+    rng = np.random.default_rng(21)
+    d = w.deconv_instance(40, 9, 2.0, 0.2, 1e-4, 5)
+    yield o.deconv_program(d["c"], d["b"])
+    d = w.lasso_instance(15, 11, 0.2, 1e-4, 6)
+    yield o.lasso_program(d["A"], d["b"], d["lam"])
+    G = rng.standard_normal((9, 4))
+    yield o.dense_program(G, rng.random(9), rng.standard_normal(4), 4, [5])
+
+
+def test_partition_merges_overlaps_and_keeps_gaps():
+    from oracle.equil import partition
+    g = partition(12, [(2, 5), (4, 7), (9, 10)])
+    assert g.tolist() == [0, 0, 1, 1, 1, 1, 1, 2, 2, 3, 4, 4]
+    assert partition(3, []).tolist() == [0, 0, 0]
+
+
+def test_groups_of_the_canonical_forms():
+    """Deconv: rows {x >= 0}, {the SOC}; columns {x}, {t}.  Lasso: the two
+    nonnegative row blocks and the SOC; columns {x}, {t}, {u}.  One dense block:
+    one group each way."""
+    from oracle.equil import groups
+    dec, las, den = _small_programs()
+    rg, cg = groups(dec)
+    assert np.bincount(rg).tolist() == [40, 40 + 9] and np.bincount(cg).tolist() == [40, 1]
+    rg, cg = groups(las)
+    assert np.bincount(rg).tolist() == [11, 11, 17] and np.bincount(cg).tolist() == [11, 11, 1]
+    rg, cg = groups(den)
+    assert np.bincount(rg).tolist() == [9] and np.bincount(cg).tolist() == [4]
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_group_norms_and_squared_apply_against_explicit(which):
+    from oracle.equil import groups, group_norms
+    prog = list(_small_programs())[which]
+    A = prog.explicit()
+    rg, cg = groups(prog)
+    F = group_norms(prog, rg, cg)
+    for g in range(F.shape[0]):
+        for h in range(F.shape[1]):
+            assert np.isclose(F[g, h], (A[np.ix_(rg == g, cg == h)] ** 2).sum(), rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_equilibrated_operator_properties(which):
+    """The scaled matrix D A E: the cone is preserved (D constant on each SOC),
+    its group RMS row norms agree across row groups and its column norms across
+    column groups (the Ruiz fixed point), the
+    structured factorisation solves I + (DAE)^T (DAE), and the scaled data are
+    sigma_b D b, sigma_c E c.  (Rows and columns cannot both reach RMS 1
+    when one group spans an m x n block: their ratio is sqrt(n / m).)"""
+    prog = list(_small_programs())[which]
+    s = o.equilibrate(prog)
+    start = prog.l
+    for qq in prog.q:
+        assert np.all(s.D[start:start + qq] == s.D[start])
+        start += qq
+    As = s.D[:, None] * prog.explicit() * s.E[None, :]
+    rn = np.linalg.norm(As, axis=1) ** 2
+    cn = np.linalg.norm(As, axis=0) ** 2
+    rms_r = np.sqrt(np.bincount(s.row_groups, rn) / np.bincount(s.row_groups))
+    rms_c = np.sqrt(np.bincount(s.col_groups, cn) / np.bincount(s.col_groups))
+    assert rms_r.max() / rms_r.min() < 1.05 and rms_c.max() / rms_c.min() < 1.05, (rms_r, rms_c)
+    sp = o.scaled_program(prog, s)
+    rng = np.random.default_rng(which)
+    r = rng.standard_normal(prog.n)
+    np.testing.assert_allclose(sp.factor().solve(r), np.linalg.solve(np.eye(prog.n) + As.T @ As, r),
+                               rtol=1e-10, atol=1e-12)
+    x = rng.standard_normal(prog.n)
+    np.testing.assert_allclose(sp.A(x), As @ x, atol=1e-12)
+    np.testing.assert_allclose(sp.b, s.sigma_b * s.D * prog.b)
+    np.testing.assert_allclose(sp.c, s.sigma_c * s.E * prog.c)
+
+
+@pytest.mark.parametrize("family", ["deconv", "lasso"])
+def test_solution_independent_of_equilibration(family):
+    """Same optimum with and without the scaling, and the reported residuals are
+    those of the returned (unscaled) point on the original data."""
+    if family == "deconv":
+        d = w.deconv_instance(60, 11, 2.0, 0.2, 1e-4, 8)
+        prog = o.deconv_program(d["c"], d["b"])
+        C, b = conv_matrix(d["c"], 60), d["b"]
+        xs, _ = nnls(C, b)
+        ref = np.linalg.norm(C @ xs - b)
+        f = lambda r: np.linalg.norm(C @ np.maximum(r.x[:60], 0) - b)
+    else:
+        d = w.lasso_instance(30, 40, 0.1, 1e-4, 12)
+        prog = o.lasso_program(d["A"], d["b"], d["lam"])
+        x0 = o.scs_solve(prog, eps=1e-8, normalize=False).x[:40]
+        pol = o.polish_lasso(d["A"], d["b"], d["lam"], x0)
+        assert pol["kkt_ok"]
+        ref = pol["obj"]
+        f = lambda r: o.lasso_objective(d["A"], d["b"], d["lam"], r.x[:40])
+    for norm in (True, False):
+        r = o.scs_solve(prog, eps=1e-9, normalize=norm, max_iters=200_000)
+        assert r.status == "solved"
+        assert abs(f(r) - ref) <= 1e-7 * (1 + ref), (norm, f(r), ref)
+        rp, rd, gap, _, _ = residuals(prog, r.x, r.y, 1.0, r.s)
+        assert np.isclose(rp, r.res_pri, rtol=1e-6, atol=1e-15)
+        assert np.isclose(rd, r.res_dual, rtol=1e-6, atol=1e-15)
+        assert max(rp, rd, gap) <= 1e-9
