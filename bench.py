@@ -93,6 +93,10 @@ def run_deconv(args, cfg):
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
     s.set_data(0, pr.b, pr.c)
     log(f"workspace {s.workspace_bytes / 2**20:.1f} MiB")
+    mfma = 0
+    if prec == P.FP32 and not args.no_autotune:
+        mfma = s.autotune(reps=10)["conv_mfma"]
+        log(f"autotune: convolution on {'matrix cores' if mfma else 'vector ALU'}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
     last = infos[-1][0]
     t_fwd = s.kernel_time(0, 20)
@@ -116,7 +120,7 @@ def run_deconv(args, cfg):
         import oracle
         prog = oracle.deconv_program(data["c"], data["b"])
         t0 = time.perf_counter()
-        fac = prog.factor()
+        fac = oracle.prepare(prog)[0].factor()   # of the equilibrated operator
         t_factor = time.perf_counter() - t0
         res = oracle.scs_solve(prog, eps=cfg["eps"], max_iters=args.cpu_iters, check_every=10, fac=fac)
         t_iter = res.solve_s / max(res.iters, 1)
@@ -136,9 +140,11 @@ def run_deconv(args, cfg):
         "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed,
         "status": last["status_name"], "max_iters_cap": args.max_iters,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "kernel": "k_conv<float> (direct convolution A and its adjoint A^T)",
+        "roofline": {"bound": "mfma" if mfma else "alu", "achieved": achieved,
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": ("k_conv_mfma (FP32 matrix-core convolution" if mfma else
+                                "k_conv<float> (direct convolution") + " A and its adjoint A^T)",
                      "flop_per_launch": {"A": flop_fwd, "AT": flop_adj},
                      "launch_us": {"A": t_fwd * 1e3, "AT": t_adj * 1e3}},
         "cpu_baseline": cpu, "verify": verify,
@@ -219,6 +225,10 @@ def run_lasso_batch(args, cfg):
     s = P.Solver(prs[0].op, prs[0].l, prs[0].q, st, batch=B, stream=stream)
     for i, pr in enumerate(prs):
         s.set_data(i, pr.b, pr.c)
+    tuned = None
+    if not args.no_autotune:
+        tuned = s.autotune(reps=10)["gemm_target_wgs"]
+        log(f"autotune: batched GEMM aims at {tuned} workgroups")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
     last = infos[-1]
     solves = B * args.steps
@@ -250,7 +260,8 @@ def run_lasso_batch(args, cfg):
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         prog = oracle.lasso_program(data["A"], data["b"][0], data["lam"][0])
-        fac = prog.factor()
+        fac = oracle.prepare(prog)[0].factor()   # the scaled operator is the same for all b
+
         tf = time.perf_counter() - t0
         nsamp = min(B, args.cpu_solves)
         t1 = time.perf_counter()
@@ -266,6 +277,7 @@ def run_lasso_batch(args, cfg):
     out = base_record(args, solves / elapsed, "solves/s", elapsed, "bf16",
                       {"workload": cfg["name"], "m": m, "n": n, "batch": B, "eps": cfg["eps"],
                        "products": "bf16 MFMA, fp32 accumulation; refinement phase bf16 hi/lo",
+                       "gemm_target_wgs": tuned,
                        "scalars": "f64"})
     out.update({
         "time_per_batch_s": elapsed / args.steps,
@@ -362,6 +374,8 @@ def main():
     ap.add_argument("--cpu-solves", type=int, default=4)
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel choices instead of timing the candidates")
     ap.add_argument("--max-iters", type=int, default=None,
                     help="cap on ADMM iterations (profiling runs; the JSON then says so)")
     ap.add_argument("--copy-calibration", type=int, default=0,

@@ -111,7 +111,15 @@ typedef struct {
                               the solver / server qualifies; 0 disables (default 65536) */
     int32_t conv_mfma;     /* 1: FP32 convolutions run on the matrix cores (16x16x4 FP32
                               MFMA over Toeplitz blocks of the taps); 0: vector ALU  */
-    int32_t reserved[4];
+    int32_t normalize;     /* 1 (default): iterate on equilibrated data D A E,
+                              sb D b, sc E c, with diagonal D (rows) and E (columns)
+                              constant on every operator block and second-order cone
+                              (Ruiz passes on the blocks' Frobenius norms, then b and
+                              c scaled to the mean row / column norm).  Termination
+                              and returned points are those of the original problem;
+                              the raw state and the diagnostic apply / normal solve
+                              are in the scaled variables.  0: data as given.     */
+    int32_t reserved[3];
 } cgs_settings;
 
 /* Per-instance result. */
@@ -161,6 +169,16 @@ int cgs_op_add_dense(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64
                      const double* a, int64_t lda, double scale);
 /* Number of blocks and the operator size. */
 int cgs_op_info(const cgs_op* op, int64_t* m, int64_t* n, int64_t* nblocks);
+/* The equilibration a solver with normalize = 1 applies to this operator and
+ * cone (host computation, no device work): d (m entries) and e (n entries)
+ * receive the row and column scalings D and E, constant on the groups of
+ * rows / columns that every block and second-order cone lies in; with b (m)
+ * and c (n) given, sigma[2] receives {sigma_b, sigma_c}, the factors of
+ * b^ = sigma_b D b and c^ = sigma_c E c.  Any output may be NULL.  The raw
+ * solver state is u^ = (sigma_b E^-1 x tau, sigma_c D^-1 y tau, tau) with
+ * v^_s = sigma_b D s tau. */
+int cgs_op_equilibrate(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
+                       const double* b, const double* c, double* d, double* e, double* sigma);
 void cgs_op_destroy(cgs_op* op);
 
 /* ---------------------------------------------------------------- solver
@@ -198,7 +216,8 @@ int cgs_solver_iterate(cgs_solver* s, int32_t iters);
 /* Primal-dual point (x = u_x/tau, y = u_y/tau, s = v_s/tau) of an instance, as
  * FP64 host arrays of n, m, m entries (any may be NULL). */
 int cgs_solver_get_solution(cgs_solver* s, int64_t inst, double* x, double* y, double* sl);
-/* Raw embedding state: u_x (n), u_y (m), v_s (m) and scal[2] = {tau, kappa}. */
+/* Raw embedding state of the (equilibrated) problem the iteration runs on:
+ * u_x (n), u_y (m), v_s (m) and scal[2] = {tau, kappa}. */
 int cgs_solver_get_state(cgs_solver* s, int64_t inst, double* ux, double* uy, double* vs,
                          double* scal);
 /* Overwrite the embedding state (warm start / resume); the next cgs_solve or
@@ -209,10 +228,11 @@ int cgs_solver_set_state(cgs_solver* s, int64_t inst, const double* ux, const do
  * (info: batch entries; status stays CGS_RUNNING unless a test passes). */
 int cgs_solver_residuals(cgs_solver* s, cgs_info* info);
 /* One operator application on the device in the working precision, for
- * instance 0's operator: out = A in (transpose = 0, in: n, out: m) or
- * out = A^T in (transpose = 1, in: m, out: n).  Host FP64 arrays. */
+ * instance 0's operator as the iteration sees it (D A E when normalize = 1):
+ * out = A in (transpose = 0, in: n, out: m) or out = A^T in (transpose = 1,
+ * in: m, out: n).  Host FP64 arrays. */
 int cgs_solver_apply(cgs_solver* s, int32_t transpose, const double* in, double* out);
-/* Conjugate gradients on (I + A^T A) z = rhs in the working precision from
+/* Conjugate gradients on (I + A^T A) z = rhs (A as in cgs_solver_apply) in the working precision from
  * z = z0 (NULL: 0) until ||r|| <= tol ||rhs|| or max_iters; host FP64 arrays of
  * n entries; *iters receives the iteration count (Section IV-B listing). */
 int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, double* z,

@@ -31,7 +31,8 @@ class Settings(C.Structure):
         ("cg_tol", C.c_double), ("cg_rate", C.c_double), ("cg_floor", C.c_double),
         ("setup_tol", C.c_double), ("setup_max_iters", C.c_int32), ("use_graph", C.c_int32),
         ("bf16_phase1_digits", C.c_int32), ("cg_adaptive", C.c_int32),
-        ("fused_max", C.c_int32), ("conv_mfma", C.c_int32), ("reserved", C.c_int32 * 4),
+        ("fused_max", C.c_int32), ("conv_mfma", C.c_int32), ("normalize", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
     @classmethod
@@ -74,6 +75,7 @@ _SIGS = {
     "cgs_op_add_conv": (C.c_int, [_P, _I64, _I64, _DP, _I64, _I64, _D]),
     "cgs_op_add_dense": (C.c_int, [_P, _I64, _I64, _I64, _I64, _DP, _I64, _D]),
     "cgs_op_info": (C.c_int, [_P, _I64P, _I64P, _I64P]),
+    "cgs_op_equilibrate": (C.c_int, [_P, C.c_int64, _I64P, C.c_int64, _DP, _DP, _DP, _DP, _DP]),
     "cgs_op_destroy": (None, [_P]),
     "cgs_settings_default": (None, [C.POINTER(Settings)]),
     "cgs_workspace_bytes": (C.c_int, [_P, _I64, _I64P, _I64, C.POINTER(Settings), _I64,
@@ -187,6 +189,19 @@ class Operator:
         self.kinds.append("dense")
         return self
 
+    def equilibrate(self, l: int, q: Sequence[int], b=None, c=None):
+        """Row / column scalings (D, E) a normalising solver uses for this
+        operator and cone, and (sigma_b, sigma_c) when b and c are given."""
+        qa = np.asarray(list(q), dtype=np.int64)
+        d, e = np.empty(self.m), np.empty(self.n)
+        sig = np.empty(2)
+        bb = None if b is None else _f64(b, self.m)
+        cc = None if c is None else _f64(c, self.n)
+        _check(lib().cgs_op_equilibrate(self._h, int(l), qa.ctypes.data_as(_I64P), len(qa),
+                                        None if bb is None else _dp(bb),
+                                        None if cc is None else _dp(cc), _dp(d), _dp(e), _dp(sig)))
+        return d, e, ((float(sig[0]), float(sig[1])) if bb is not None else None)
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h and _LIB is not None:
@@ -260,6 +275,8 @@ class Solver:
         return x, y, s
 
     def state(self, inst: int = 0):
+        """Raw embedding state (u_x, u_y, tau, v_s, kappa) of the problem the
+        iteration runs on (the equilibrated one unless normalize = 0)."""
         ux, uy, vs, sc = np.empty(self.n), np.empty(self.m), np.empty(self.m), np.empty(2)
         _check(lib().cgs_solver_get_state(self._h, inst, _dp(ux), _dp(uy), _dp(vs), _dp(sc)))
         return ux, uy, float(sc[0]), vs, float(sc[1])
@@ -275,6 +292,8 @@ class Solver:
         return [i.as_dict() for i in infos]
 
     def apply(self, v, transpose: bool = False) -> np.ndarray:
+        """A v (or A^T v) on the device, A as the iteration sees it (D A E when
+        normalize = 1)."""
         v = _f64(v, self.m if transpose else self.n)
         out = np.empty(self.n if transpose else self.m)
         _check(lib().cgs_solver_apply(self._h, 1 if transpose else 0, _dp(v), _dp(out)))

@@ -87,6 +87,7 @@ int solver_layout(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, con
 struct cgs_solver {
     cgs::Engine eng;
     cgs::OpDev opdev;
+    cgs::Scaling scl;
     int64_t n = 0, m = 0, batch = 0;
     std::vector<char> has_data;
 };
@@ -142,6 +143,7 @@ int cgs_op_add_identity(cgs_op* op, int64_t row0, int64_t col0, int64_t len, dou
     b.col0 = col0;
     b.rows = b.cols = len;
     b.scale = scale;
+    b.frob2 = (double)len;
     op->blocks.push_back(std::move(b));
     return CGS_OK;
 }
@@ -163,6 +165,9 @@ int cgs_op_add_conv(cgs_op* op, int64_t row0, int64_t col0, const double* taps, 
     b.n_in = n_in;
     b.scale = scale;
     b.data.assign(taps, taps + k);
+    b.frob2 = 0.0;   // full convolution: every column holds all k taps
+    for (int64_t t = 0; t < k; ++t) b.frob2 += taps[t] * taps[t];
+    b.frob2 *= (double)n_in;
     op->blocks.push_back(std::move(b));
     return CGS_OK;
 }
@@ -189,6 +194,8 @@ int cgs_op_add_dense(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64
         if (!all_finite(src, cols)) return fail(CGS_EINVAL, "matrix row %lld has a non-finite value", (long long)i);
         std::memcpy(b.data.data() + i * cols, src, (size_t)cols * sizeof(double));
     }
+    b.frob2 = 0.0;
+    for (double v : b.data) b.frob2 += v * v;
     op->blocks.push_back(std::move(b));
     return CGS_OK;
 }
@@ -198,6 +205,27 @@ int cgs_op_info(const cgs_op* op, int64_t* m, int64_t* n, int64_t* nblocks) {
     if (m) *m = op->m;
     if (n) *n = op->n;
     if (nblocks) *nblocks = (int64_t)op->blocks.size();
+    return CGS_OK;
+}
+
+int cgs_op_equilibrate(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
+                       const double* b, const double* c, double* d, double* e, double* sigma) {
+    if (!op) return fail(CGS_EINVAL, "operator is null");
+    CGS_TRY(cgs::validate_cone(op->m, l, q, nq));
+    if ((b == nullptr) != (c == nullptr)) return fail(CGS_EINVAL, "give both b and c, or neither");
+    cgs::Scaling scl;
+    cgs::compute_scaling(*op, l, q, nq, true, &scl);
+    std::vector<double> dv((size_t)op->m), ev((size_t)op->n), bh((size_t)op->m), ch((size_t)op->n);
+    std::vector<double> zb((size_t)op->m, 0.0), zc((size_t)op->n, 0.0);
+    double sb = 1.0, sc = 1.0;
+    cgs::scale_data(scl, op->m, op->n, b ? b : zb.data(), c ? c : zc.data(), dv.data(), ev.data(),
+                    bh.data(), ch.data(), &sb, &sc);
+    if (d) std::memcpy(d, dv.data(), dv.size() * sizeof(double));
+    if (e) std::memcpy(e, ev.data(), ev.size() * sizeof(double));
+    if (sigma && b) {
+        sigma[0] = sb;
+        sigma[1] = sc;
+    }
     return CGS_OK;
 }
 
@@ -223,6 +251,33 @@ void cgs_settings_default(cgs_settings* st) {
     st->cg_adaptive = 1;
     st->fused_max = 65536;
     st->conv_mfma = 1;
+    st->normalize = 1;
+}
+
+// Equilibrated data of one instance written into its region (layout of
+// common.hpp): b^ = sb D b and c^ = sc E c, the scaling vectors D and E, and
+// the data scales sb, sc.
+static int upload_instance_data(cgs::Engine& e, const cgs::Scaling& scl, char* base, int64_t n,
+                                int64_t m, const double* b, const double* c) {
+    std::vector<double> dv, ev, bh, ch;
+    try {
+        dv.resize((size_t)m); bh.resize((size_t)m);
+        ev.resize((size_t)n); ch.resize((size_t)n);
+    } catch (...) {
+        return fail(CGS_ENOMEM, "host allocation failed");
+    }
+    double sc2[2];
+    cgs::scale_data(scl, m, n, b, c, dv.data(), ev.data(), bh.data(), ch.data(), &sc2[0], &sc2[1]);
+    const size_t sz = cgs::elem_bytes(e.precision);
+    const int64_t nxs = cgs::round_up(n, cgs::XY_ALIGN), nys = cgs::round_up(m, cgs::XY_ALIGN);
+    auto xv = [&](int k) { return base + cgs::REGION_HDR + (size_t)k * nxs * sz; };
+    auto yv = [&](int k) { return base + cgs::REGION_HDR + ((size_t)cgs::NXV * nxs + (size_t)k * nys) * sz; };
+    CGS_TRY(cgs::upload_f64(e.stg, e.stream, bh.data(), m, e.prec, yv(cgs::YB)));
+    CGS_TRY(cgs::upload_f64(e.stg, e.stream, dv.data(), m, e.prec, yv(cgs::YD)));
+    CGS_TRY(cgs::upload_f64(e.stg, e.stream, ch.data(), n, e.prec, xv(cgs::XC)));
+    CGS_TRY(cgs::upload_f64(e.stg, e.stream, ev.data(), n, e.prec, xv(cgs::XE)));
+    CGS_TRY(cgs::upload_raw(e.stg, e.stream, sc2, sizeof sc2, base + cgs::SC_SB * sizeof(double)));
+    return CGS_OK;
 }
 
 // ---------------------------------------------------------------- solver
@@ -265,7 +320,8 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
         e.panel_lo = (uint16_t*)p; p += L.panel;
         e.gemm_part = (float*)p; p += L.part;
     }
-    CGS_TRY(cgs::op_upload(*op, st->precision, opdata, e.stg, e.stream, &s->opdev));
+    cgs::compute_scaling(*op, l, q, nq, st->normalize != 0, &s->scl);
+    CGS_TRY(cgs::op_upload(*op, st->precision, opdata, e.stg, e.stream, &s->opdev, s->scl.blk.data()));
     std::vector<cgs::InstRec> recs((size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
         recs[i].base = p + (size_t)i * L.region;
@@ -296,8 +352,7 @@ int cgs_solver_set_data(cgs_solver* s, int64_t inst, const double* b, const doub
     if (!all_finite(c, s->n)) return fail(CGS_EINVAL, "c has a non-finite entry");
     cgs::Engine& e = s->eng;
     CGS_TRY(e.reset((int)inst));
-    CGS_TRY(cgs::upload_f64(e.stg, e.stream, b, s->m, e.prec, e.yptr((int)inst, cgs::YB)));
-    CGS_TRY(cgs::upload_f64(e.stg, e.stream, c, s->n, e.prec, e.xptr((int)inst, cgs::XC)));
+    CGS_TRY(upload_instance_data(e, s->scl, e.recs[(size_t)inst].base, s->n, s->m, b, c));
     CGS_HIP(hipStreamSynchronize(e.stream));
     s->has_data[(size_t)inst] = 1;
     return CGS_OK;
@@ -748,18 +803,15 @@ int cgs_server_submit(cgs_server* sv, const cgs_op* op, int64_t l, const int64_t
     r->q.assign(q, q + nq);
     r->t_submit = now_s();
     char* base = sv->arena + off;
-    int rc = cgs::op_upload(*op, e.precision, base + region, e.stg, e.stream, &r->opdev);
+    cgs::Scaling scl;
+    cgs::compute_scaling(*op, l, q, nq, e.st.normalize != 0, &scl);
+    int rc = cgs::op_upload(*op, e.precision, base + region, e.stg, e.stream, &r->opdev, scl.blk.data());
     if (rc != CGS_OK) {
         arena_free(sv, off, bytes);
         return rc;
     }
-    // b and c go straight into the region (layout of common.hpp)
-    const size_t sz = cgs::elem_bytes(e.precision);
-    const int64_t nxs = cgs::round_up(op->n, cgs::XY_ALIGN), nys = cgs::round_up(op->m, cgs::XY_ALIGN);
-    char* xc = base + cgs::REGION_HDR + (size_t)cgs::XC * nxs * sz;
-    char* yb = base + cgs::REGION_HDR + ((size_t)cgs::NXV * nxs + (size_t)cgs::YB * nys) * sz;
-    rc = cgs::upload_f64(e.stg, e.stream, b, op->m, e.prec, yb);
-    if (rc == CGS_OK) rc = cgs::upload_f64(e.stg, e.stream, c, op->n, e.prec, xc);
+    // the equilibrated b and c go straight into the region
+    rc = upload_instance_data(e, scl, base, op->n, op->m, b, c);
     if (rc != CGS_OK) {
         arena_free(sv, off, bytes);
         return rc;

@@ -7,6 +7,8 @@
 //
 // X vectors have the length n of the variable, Y vectors the length m of the
 // constraint rows; nxs / nys are those lengths rounded up to XY_ALIGN elements.
+// The iteration runs on the equilibrated data (D A E, sb D b, sc E c); the
+// termination test and the returned points are those of the original problem.
 // Kernels walk *tile tables*: every tile lies inside one instance, so a single
 // launch covers all instances, and the per-instance arithmetic (including the
 // fixed-order reductions) does not depend on which other instances are in it.
@@ -28,6 +30,7 @@ enum XVec : int {
     XH,       // CG right-hand side
     XT,       // scratch (A^T y for residuals / diagnostics)
     XK,       // (I + A^T A) z, carried through the CG updates
+    XE,       // column scaling E of the equilibrated operator D A E
     NXV
 };
 // Y-space vectors (length m)
@@ -40,6 +43,7 @@ enum YVec : int {
     YZ,       // z_y = w_y + A z_x
     YT,       // scratch (A p, A u_x)
     YA,       // A z, carried through the CG updates
+    YD,       // row scaling D of the equilibrated operator D A E
     NYV
 };
 
@@ -63,9 +67,11 @@ enum Scal : int {
     SC_CUX, SC_BUY,                            // raw c^T u_x, b^T u_y at the last check
     SC_CGMAX,                                  // most CG iterations of a step since the last check
     SC_CGMAXLAST,                              // ... over the previous check interval
+    SC_SB, SC_SC,                              // data scales: b^ = sb D b, c^ = sc E c
     NSC_USED
 };
 constexpr int NSC = 32;      // doubles reserved per instance (256 bytes)
+static_assert(NSC_USED <= NSC, "scalar slots");
 constexpr int NCNT = 64;     // int counters reserved per instance (256 bytes)
 constexpr int XY_ALIGN = 64; // elements
 constexpr int REGION_HDR = NSC * 8 + NCNT * 4;  // 512 bytes

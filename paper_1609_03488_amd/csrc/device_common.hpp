@@ -148,6 +148,53 @@ DEVI void conv_step(T (&acc)[R], const T (&lo)[R], const T (&hi)[R], const T (&t
 }
 
 // relaxed point minus v for a Y entry
+// Termination test from the six sums of a check on the scaled iterate
+// (u^, v^) with A^ = D A E, b^ = sb D b, c^ = sc E c:
+//   y0 = ||(A^ u^_x + v^_s - tau b^) / D||^2   y1 = ||(A^ u^_x + v^_s) / D||^2   y2 = b^T u^_y
+//   x0 = ||(A^T u^_y + tau c^) / E||^2          x1 = ||A^T u^_y / E||^2           x2 = c^T u^_x
+// The original problem's point is x = E u^_x / (sb tau), y = D u^_y / (sc tau),
+// s = v^_s / (D sb tau), so its relative residuals are sqrt(y0) / (sb tau (1 + ||b||))
+// and sqrt(x0) / (sc tau (1 + ||c||)), and c^T x = x2 / (sb sc tau); the
+// certificate rays (the same points without the 1 / tau) are tested the same way.
+struct CheckOut {
+    double rp, rd, gap, cx, by;   // residuals, gap, c^T x, b^T y (tau > 0)
+    double cux, buy;              // c^T x_ray, b^T y_ray
+    double status;                // 0: continue, else the CGS_* outcome
+};
+DEVI CheckOut check_outcome(gptr<const double> sc, double tau, double kap, double iter, double y0,
+                            double y1, double y2, double x0, double x1, double x2, double eps,
+                            int max_iters) {
+    CheckOut o;
+    const double sb = sc[SC_SB], scc = sc[SC_SC];
+    o.cux = x2 / (sb * scc);
+    o.buy = y2 / (sb * scc);
+    o.rp = o.rd = o.gap = INFINITY;
+    o.cx = o.by = NAN;
+    o.status = 0.0;
+    const bool finite = std::isfinite(y0) && std::isfinite(y1) && std::isfinite(y2) &&
+                        std::isfinite(x0) && std::isfinite(x1) && std::isfinite(x2) &&
+                        std::isfinite(tau) && std::isfinite(kap);
+    if (!finite) {
+        o.status = 5.0;   // CGS_NUMERICAL
+        return o;
+    }
+    if (tau > 0.0) {
+        o.rp = sqrt(y0) / (sb * tau) / (1.0 + sc[SC_NB]);
+        o.rd = sqrt(x0) / (scc * tau) / (1.0 + sc[SC_NC]);
+        o.cx = o.cux / tau;
+        o.by = o.buy / tau;
+        o.gap = fabs(o.cx + o.by) / (1.0 + fabs(o.cx) + fabs(o.by));
+        if (o.rp <= eps && o.rd <= eps && o.gap <= eps) o.status = 1.0;   // CGS_SOLVED
+    }
+    if (o.status == 0.0 && tau < kap) {
+        // ||A^T y_ray|| = sqrt(x1) / sc,  ||A x_ray + s_ray|| = sqrt(y1) / sb
+        if (o.buy < 0.0 && sqrt(x1) / scc <= eps * (-o.buy)) o.status = 3.0;        // INFEASIBLE
+        else if (o.cux < 0.0 && sqrt(y1) / sb <= eps * (-o.cux)) o.status = 4.0;   // UNBOUNDED
+    }
+    if (o.status == 0.0 && iter >= (double)max_iters) o.status = 2.0;   // MAX_ITERS
+    return o;
+}
+
 template <typename T>
 DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, double& ubar) {
     const double uy = (double)yvec<T>(d, YU)[i];

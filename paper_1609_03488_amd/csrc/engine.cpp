@@ -51,6 +51,7 @@ int validate_settings(const cgs_settings* s) {
     if (s->setup_max_iters < 1) return fail(CGS_EINVAL, "setup_max_iters must be >= 1");
     if (s->bf16_phase1_digits < 0 || s->bf16_phase1_digits > 15)
         return fail(CGS_EINVAL, "bf16_phase1_digits must be in [0, 15]");
+    if (s->normalize != 0 && s->normalize != 1) return fail(CGS_EINVAL, "normalize must be 0 or 1");
     return CGS_OK;
 }
 
@@ -91,13 +92,124 @@ size_t op_dev_bytes(const cgs_op& op, int precision) {
     return tot;
 }
 
-void op_dev_shape(const cgs_op& op, int precision, OpDev* out) {
+// ---------------------------------------------------------------- equilibration
+namespace {
+// Contiguous groups of [0, len): intervals that share a position merge;
+// uncovered runs are groups of their own.  Returns the group starts (+ len).
+std::vector<int64_t> partition(int64_t len, std::vector<std::pair<int64_t, int64_t>> iv) {
+    std::sort(iv.begin(), iv.end());
+    std::vector<std::pair<int64_t, int64_t>> merged;
+    for (const auto& p : iv) {
+        if (p.second <= p.first) continue;
+        if (!merged.empty() && p.first < merged.back().second)
+            merged.back().second = std::max(merged.back().second, p.second);
+        else
+            merged.push_back(p);
+    }
+    std::vector<int64_t> lo;
+    int64_t pos = 0;
+    for (const auto& p : merged) {
+        if (p.first > pos) lo.push_back(pos);
+        lo.push_back(p.first);
+        pos = p.second;
+    }
+    if (pos < len || lo.empty()) lo.push_back(pos);
+    lo.push_back(len);
+    return lo;
+}
+int group_of(const std::vector<int64_t>& lo, int64_t i) {
+    return (int)(std::upper_bound(lo.begin(), lo.end(), i) - lo.begin()) - 1;
+}
+}  // namespace
+
+void compute_scaling(const cgs_op& op, int64_t l, const int64_t* q, int64_t nq, bool on,
+                     Scaling* out) {
+    constexpr int kPasses = 20;
+    constexpr double kMin = 1e-4, kMax = 1e4;
+    std::vector<std::pair<int64_t, int64_t>> rows, cols;
+    for (const auto& b : op.blocks) {
+        rows.emplace_back(b.row0, b.row0 + b.rows);
+        cols.emplace_back(b.col0, b.col0 + b.cols);
+    }
+    int64_t start = l;
+    for (int64_t i = 0; i < nq; ++i) {
+        rows.emplace_back(start, start + q[i]);
+        start += q[i];
+    }
+    out->row_lo = partition(op.m, rows);
+    out->col_lo = partition(op.n, cols);
+    const int p = (int)out->row_lo.size() - 1, r = (int)out->col_lo.size() - 1;
+    out->d.assign(p, 1.0);
+    out->e.assign(r, 1.0);
+    out->blk.assign(op.blocks.size(), 1.0);
+    out->mean_row = out->mean_col = 1.0;
+    out->on = on;
+    if (!on) return;
+    std::vector<int> bg(op.blocks.size()), bh(op.blocks.size());
+    std::vector<double> F((size_t)p * r, 0.0), R(p), Cn(r);
+    for (size_t k = 0; k < op.blocks.size(); ++k) {
+        const HostBlock& b = op.blocks[k];
+        bg[k] = group_of(out->row_lo, b.row0);
+        bh[k] = group_of(out->col_lo, b.col0);
+        F[(size_t)bg[k] * r + bh[k]] += b.frob2 * b.scale * b.scale;
+    }
+    for (int g = 0; g < p; ++g) R[g] = (double)(out->row_lo[g + 1] - out->row_lo[g]);
+    for (int h = 0; h < r; ++h) Cn[h] = (double)(out->col_lo[h + 1] - out->col_lo[h]);
+    std::vector<double>& D = out->d;
+    std::vector<double>& E = out->e;
+    auto row_rms = [&](int g) {
+        double s = 0.0;
+        for (int h = 0; h < r; ++h) s += F[(size_t)g * r + h] * E[h] * E[h];
+        return std::sqrt(D[g] * D[g] * s / R[g]);
+    };
+    auto col_rms = [&](int h) {
+        double s = 0.0;
+        for (int g = 0; g < p; ++g) s += F[(size_t)g * r + h] * D[g] * D[g];
+        return std::sqrt(E[h] * E[h] * s / Cn[h]);
+    };
+    for (int pass = 0; pass < kPasses; ++pass) {
+        std::vector<double> rho(p), gam(r);
+        for (int g = 0; g < p; ++g) rho[g] = row_rms(g);
+        for (int g = 0; g < p; ++g)
+            if (rho[g] > 0.0) D[g] /= std::sqrt(std::min(std::max(rho[g], kMin), kMax));
+        for (int h = 0; h < r; ++h) gam[h] = col_rms(h);
+        for (int h = 0; h < r; ++h)
+            if (gam[h] > 0.0) E[h] /= std::sqrt(std::min(std::max(gam[h], kMin), kMax));
+    }
+    double mr = 0.0, mc = 0.0;
+    for (int g = 0; g < p; ++g) mr += R[g] * row_rms(g);
+    for (int h = 0; h < r; ++h) mc += Cn[h] * col_rms(h);
+    out->mean_row = mr / (double)op.m;
+    out->mean_col = mc / (double)op.n;
+    for (size_t k = 0; k < op.blocks.size(); ++k) out->blk[k] = D[bg[k]] * E[bh[k]];
+}
+
+void scale_data(const Scaling& s, int64_t m, int64_t n, const double* b, const double* c,
+                double* dv, double* ev, double* bh, double* ch, double* sb, double* sc) {
+    for (size_t g = 0; g + 1 < s.row_lo.size(); ++g)
+        for (int64_t i = s.row_lo[g]; i < s.row_lo[g + 1]; ++i) dv[i] = s.d[g];
+    for (size_t h = 0; h + 1 < s.col_lo.size(); ++h)
+        for (int64_t j = s.col_lo[h]; j < s.col_lo[h + 1]; ++j) ev[j] = s.e[h];
+    double nb = 0.0, nc = 0.0;
+    for (int64_t i = 0; i < m; ++i) nb += (dv[i] * b[i]) * (dv[i] * b[i]);
+    for (int64_t j = 0; j < n; ++j) nc += (ev[j] * c[j]) * (ev[j] * c[j]);
+    constexpr double kDataMin = 1e-4;
+    *sb = s.on ? s.mean_row / std::max(std::sqrt(nb), kDataMin) : 1.0;
+    *sc = s.on ? s.mean_col / std::max(std::sqrt(nc), kDataMin) : 1.0;
+    for (int64_t i = 0; i < m; ++i) bh[i] = *sb * dv[i] * b[i];
+    for (int64_t j = 0; j < n; ++j) ch[j] = *sc * ev[j] * c[j];
+}
+
+void op_dev_shape(const cgs_op& op, int precision, OpDev* out, const double* mult) {
     out->ids.clear();
     out->convs.clear();
     out->dense.clear();
+    size_t bi = 0;
     for (const auto& b : op.blocks) {
+        const double scale = b.scale * (mult ? mult[bi] : 1.0);
+        ++bi;
         if (b.kind == CGS_BLOCK_IDENTITY) {
-            out->ids.push_back(IdBlock{b.row0, b.col0, b.rows, b.scale});
+            out->ids.push_back(IdBlock{b.row0, b.col0, b.rows, scale});
         } else if (b.kind == CGS_BLOCK_CONV) {
             ConvBlock cb{};
             cb.row0 = b.row0;
@@ -105,7 +217,7 @@ void op_dev_shape(const cgs_op& op, int precision, OpDev* out) {
             cb.n_in = b.n_in;
             cb.k = b.k;
             cb.kpad = round_up(b.k, conv_r(precision));
-            cb.scale = b.scale;
+            cb.scale = scale;
             out->convs.push_back(cb);
         } else {
             DenseBlock db{};
@@ -115,15 +227,15 @@ void op_dev_shape(const cgs_op& op, int precision, OpDev* out) {
             db.cols = b.cols;
             db.ld = dense_ld(b.cols);
             db.ldt = dense_ld(b.rows);
-            db.scale = b.scale;
+            db.scale = scale;
             out->dense.push_back(db);
         }
     }
 }
 
 int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hipStream_t st,
-              OpDev* out) {
-    op_dev_shape(op, precision, out);
+              OpDev* out, const double* mult) {
+    op_dev_shape(op, precision, out, mult);
     const int prec = work_prec(precision);
     const size_t sz = elem_bytes(precision);
     char* p = dst;
@@ -192,6 +304,14 @@ int upload_f64(const Staging& stg, hipStream_t st, const double* src, int64_t n,
         CGS_HIP(hipGetLastError());
         CGS_HIP(hipStreamSynchronize(st));
     }
+    return CGS_OK;
+}
+
+int upload_raw(const Staging& stg, hipStream_t st, const void* src, size_t bytes, void* dst) {
+    if (bytes > (size_t)stg.cap * sizeof(double)) return fail(CGS_ENOMEM, "staging too small");
+    std::memcpy(stg.host, src, bytes);
+    CGS_HIP(hipMemcpyAsync(dst, stg.host, bytes, hipMemcpyHostToDevice, st));
+    CGS_HIP(hipStreamSynchronize(st));
     return CGS_OK;
 }
 

@@ -43,6 +43,7 @@ struct HostBlock {
     int64_t row0, col0, rows, cols;
     int64_t k, n_in;          // conv
     double scale;
+    double frob2;             // sum of squares of the entries, scale excluded
     std::vector<double> data; // taps (k) or dense rows x cols (packed)
 };
 
@@ -68,6 +69,27 @@ struct Staging {
 };
 int64_t staging_doubles(const cgs_op& op, int64_t max_vec);
 
+// ---------------------------------------------------------------- equilibration
+// Diagonal scaling D (rows) and E (columns), constant on groups: the coarsest
+// contiguous partitions in which every block and every second-order cone (rows)
+// or every block (columns) lies inside one group.  Ruiz passes on the group
+// matrix F[g][h] = sum of squared entries of the blocks in row group g and
+// column group h; b and c are then scaled to the mean row / column norm.
+struct Scaling {
+    std::vector<int64_t> row_lo;   // group g: rows [row_lo[g], row_lo[g + 1])
+    std::vector<double> d;
+    std::vector<int64_t> col_lo;
+    std::vector<double> e;
+    std::vector<double> blk;       // D_g E_h of every operator block
+    double mean_row = 1.0, mean_col = 1.0;
+    bool on = false;
+};
+void compute_scaling(const cgs_op& op, int64_t l, const int64_t* q, int64_t nq, bool on,
+                     Scaling* out);
+// Expanded D (m), E (n), b^ = sb D b, c^ = sc E c; returns {sb, sc}.
+void scale_data(const Scaling& s, int64_t m, int64_t n, const double* b, const double* c,
+                double* dv, double* ev, double* bh, double* ch, double* sb, double* sc);
+
 // ---------------------------------------------------------------- device operator data
 struct OpDev {
     std::vector<IdBlock> ids;
@@ -75,10 +97,13 @@ struct OpDev {
     std::vector<DenseBlock> dense;
 };
 size_t op_dev_bytes(const cgs_op& op, int precision);
-// Metadata only (null data pointers): used to size tables.
-void op_dev_shape(const cgs_op& op, int precision, OpDev* out);
+// Metadata only (null data pointers): used to size tables.  `mult` (nullable):
+// per-block factor applied to the block's scale (the equilibration).
+void op_dev_shape(const cgs_op& op, int precision, OpDev* out, const double* mult = nullptr);
 int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hipStream_t st,
-              OpDev* out);
+              OpDev* out, const double* mult = nullptr);
+// Raw byte copy host -> device through the pinned staging buffer (synchronises).
+int upload_raw(const Staging& stg, hipStream_t st, const void* src, size_t bytes, void* dst);
 
 // Bytes of one instance's region (scalars, counters, X and Y vectors).
 size_t region_bytes(int64_t n, int64_t m, int precision);

@@ -229,53 +229,37 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         f_apply<T>(tb, d, 1, XT, YU, -1, 1.0, fa.kc, fsmem);   // A^T u_y
         double y0 = 0, y1 = 0, y2 = 0, x0 = 0, x1 = 0, x2 = 0;
         gptr<const T> aty = xvec<T>(d, XT);
+        gptr<const T> dr = yvec<T>(d, YD);
+        gptr<const T> ec = xvec<T>(d, XE);
         for (int64_t i = tid; i < m; i += FNT) {
-            const double e = (double)ty[i] + (double)vs[i];
-            const double rp = e - tau * (double)by[i];
+            const double w = 1.0 / (double)dr[i];
+            const double e = ((double)ty[i] + (double)vs[i]) * w;
+            const double rp = e - tau * (double)by[i] * w;
             y0 = fma(rp, rp, y0);
             y1 = fma(e, e, y1);
             y2 = fma((double)by[i], (double)uy[i], y2);
         }
         for (int64_t i = tid; i < n; i += FNT) {
-            const double e = (double)aty[i];
-            const double rd = e + tau * (double)cx[i];
+            const double w = 1.0 / (double)ec[i];
+            const double e = (double)aty[i] * w;
+            const double rd = e + tau * (double)cx[i] * w;
             x0 = fma(rd, rd, x0);
             x1 = fma(e, e, x1);
             x2 = fma((double)cx[i], (double)ux[i], x2);
         }
         y0 = bsum(y0, sh); y1 = bsum(y1, sh); y2 = bsum(y2, sh);
         x0 = bsum(x0, sh); x1 = bsum(x1, sh); x2 = bsum(x2, sh);
-        const bool finite = std::isfinite(y0) && std::isfinite(y1) && std::isfinite(y2) &&
-                            std::isfinite(x0) && std::isfinite(x1) && std::isfinite(x2) &&
-                            std::isfinite(tau) && std::isfinite(kap);
+        const CheckOut co = check_outcome(sc, tau, kap, iter, y0, y1, y2, x0, x1, x2, fa.eps,
+                                          fa.max_iters);
+        status = co.status;
         if (tid == 0) {
-            sc[SC_CUX] = x2;
-            sc[SC_BUY] = y2;
-        }
-        if (!finite) {
-            status = 5.0;
-        } else {
-            if (tau > 0.0) {
-                const double rp = sqrt(y0) / tau / (1.0 + sc[SC_NB]);
-                const double rd = sqrt(x0) / tau / (1.0 + sc[SC_NC]);
-                const double cxv = x2 / tau, byv = y2 / tau;
-                const double gap = fabs(cxv + byv) / (1.0 + fabs(cxv) + fabs(byv));
-                if (tid == 0) {
-                    sc[SC_RP] = rp;
-                    sc[SC_RD] = rd;
-                    sc[SC_GAP] = gap;
-                    sc[SC_CX] = cxv;
-                    sc[SC_BY] = byv;
-                }
-                if (rp <= fa.eps && rd <= fa.eps && gap <= fa.eps) status = 1.0;
-            } else if (tid == 0) {
-                sc[SC_RP] = sc[SC_RD] = sc[SC_GAP] = INFINITY;
-            }
-            if (status == 0.0 && tau < kap) {
-                if (y2 < 0.0 && sqrt(x1) <= fa.eps * (-y2)) status = 3.0;
-                else if (x2 < 0.0 && sqrt(y1) <= fa.eps * (-x2)) status = 4.0;
-            }
-            if (status == 0.0 && iter >= (double)fa.max_iters) status = 2.0;
+            sc[SC_CUX] = co.cux;
+            sc[SC_BUY] = co.buy;
+            sc[SC_RP] = co.rp;
+            sc[SC_RD] = co.rd;
+            sc[SC_GAP] = co.gap;
+            sc[SC_CX] = co.cx;
+            sc[SC_BY] = co.by;
         }
         if (status == 0.0) {
             // exact recomputation of the carried products of the warm start

@@ -354,8 +354,9 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
     }
 }
 
-// Termination test (relative 2-norm criteria, or the HSDE certificates).
-// YT holds A u_x and XT holds A^T u_y on entry.
+// Termination test (relative 2-norm criteria, or the HSDE certificates), in
+// the original problem's units: the row sums are divided by D, the column sums
+// by E (sums listed at check_outcome).  YT holds A u_x and XT holds A^T u_y on entry.
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max_iters) {
     __shared__ double sh[VEC_NT / 64];
@@ -371,9 +372,11 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
         gptr<const T> vs = yvec<T>(d, YV);
         gptr<const T> b = yvec<T>(d, YB);
         gptr<const T> uy = yvec<T>(d, YU);
+        gptr<const T> dr = yvec<T>(d, YD);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            const double e = (double)au[i] + (double)vs[i];
-            const double rp = e - tau * (double)b[i];
+            const double w = 1.0 / (double)dr[i];
+            const double e = ((double)au[i] + (double)vs[i]) * w;
+            const double rp = e - tau * (double)b[i] * w;
             s0 = fma(rp, rp, s0);
             s1 = fma(e, e, s1);
             s2 = fma((double)b[i], (double)uy[i], s2);
@@ -382,9 +385,11 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
         gptr<const T> aty = xvec<T>(d, XT);
         gptr<const T> c = xvec<T>(d, XC);
         gptr<const T> ux = xvec<T>(d, XU);
+        gptr<const T> ec = xvec<T>(d, XE);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            const double e = (double)aty[i];
-            const double rd = e + tau * (double)c[i];
+            const double w = 1.0 / (double)ec[i];
+            const double e = (double)aty[i] * w;
+            const double rd = e + tau * (double)c[i] * w;
             s0 = fma(rd, rd, s0);
             s1 = fma(e, e, s1);
             s2 = fma((double)c[i], (double)ux[i], s2);
@@ -493,49 +498,26 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
             break;
         }
         case FIN_RESID: {
-            const double eps = fa.a0;
-            const int max_iters = fa.i0;
-            const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
-            double status = 0.0;
-            sc[SC_CUX] = x2;
-            sc[SC_BUY] = y2;
+            const CheckOut co = check_outcome(sc, sc[SC_TAU], sc[SC_KAPPA], sc[SC_ITER], y0, y1, y2,
+                                              x0, x1, x2, fa.a0, fa.i0);
+            sc[SC_CUX] = co.cux;
+            sc[SC_BUY] = co.buy;
             sc[SC_CGMAXLAST] = sc[SC_CGMAX];
             sc[SC_CGMAX] = 0.0;
-            const bool finite = std::isfinite(y0) && std::isfinite(y1) && std::isfinite(y2) &&
-                                std::isfinite(x0) && std::isfinite(x1) && std::isfinite(x2) &&
-                                std::isfinite(tau) && std::isfinite(kap);
-            if (!finite) {
-                status = 5.0;   // CGS_NUMERICAL
-            } else {
-                if (tau > 0.0) {
-                    const double rp = sqrt(y0) / tau / (1.0 + sc[SC_NB]);
-                    const double rd = sqrt(x0) / tau / (1.0 + sc[SC_NC]);
-                    const double cx = x2 / tau, by = y2 / tau;
-                    const double gap = fabs(cx + by) / (1.0 + fabs(cx) + fabs(by));
-                    sc[SC_RP] = rp;
-                    sc[SC_RD] = rd;
-                    sc[SC_GAP] = gap;
-                    sc[SC_CX] = cx;
-                    sc[SC_BY] = by;
-                    if (rp <= eps && rd <= eps && gap <= eps) status = 1.0;   // CGS_SOLVED
-                } else {
-                    sc[SC_RP] = sc[SC_RD] = sc[SC_GAP] = INFINITY;
-                }
-                if (status == 0.0 && tau < kap) {
-                    if (y2 < 0.0 && sqrt(x1) <= eps * (-y2)) status = 3.0;        // INFEASIBLE
-                    else if (x2 < 0.0 && sqrt(y1) <= eps * (-x2)) status = 4.0;  // UNBOUNDED
-                }
-                if (status == 0.0 && sc[SC_ITER] >= (double)max_iters) status = 2.0;  // MAX_ITERS
-            }
-            if (status != 0.0) {
-                sc[SC_STATUS] = status;
+            sc[SC_RP] = co.rp;
+            sc[SC_RD] = co.rd;
+            sc[SC_GAP] = co.gap;
+            sc[SC_CX] = co.cx;
+            sc[SC_BY] = co.by;
+            if (co.status != 0.0) {
+                sc[SC_STATUS] = co.status;
                 sc[SC_ACTIVE] = 0.0;
             }
             break;
         }
-        case FIN_NORMS:
-            sc[SC_NB] = sqrt(y0);
-            sc[SC_NC] = sqrt(x0);
+        case FIN_NORMS:   // of the original b = b^ / (sb D) and c = c^ / (sc E)
+            sc[SC_NB] = sqrt(y0) / sc[SC_SB];
+            sc[SC_NC] = sqrt(x0) / sc[SC_SC];
             break;
         case FIN_ETA:
             sc[SC_ETA] = 1.0 + x0 + y0;
@@ -586,7 +568,10 @@ __global__ __launch_bounds__(VEC_NT) void k_reset(Tables tb, int only) {
         }
         if (xt.index == d.xt0 && threadIdx.x == 0) {
             gptr<double> sc = scal(d);
+            const double sb = sc[SC_SB], scc = sc[SC_SC];   // data, like b and c
             for (int j = 0; j < NSC; ++j) sc[j] = 0.0;
+            sc[SC_SB] = sb;
+            sc[SC_SC] = scc;
             sc[SC_TAU] = 1.0;
             sc[SC_KAPPA] = 1.0;
             sc[SC_ACTIVE] = 1.0;
@@ -605,9 +590,12 @@ __global__ __launch_bounds__(VEC_NT) void k_norms(Tables tb, int gate) {
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
     gptr<const T> v = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
+    gptr<const T> w = xt.is_y ? yvec<T>(d, YD) : xvec<T>(d, XE);
     double s0 = 0.0;
-    for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
-        s0 = fma((double)v[i], (double)v[i], s0);
+    for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT) {
+        const double e = (double)v[i] / (double)w[i];
+        s0 = fma(e, e, s0);
+    }
     s0 = block_sum<VEC_NT>(s0, sh);
     double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
     if (threadIdx.x == 0) part[0] = s0;
@@ -650,6 +638,9 @@ __global__ __launch_bounds__(VEC_NT) void k_copy(Tables tb, int is_y, int dst, i
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) o[i] = s[i];
 }
 
+// Points of the original problem (what 0: x, 1: y, 2: s; rays scaled by
+// -c^T x_ray or -b^T y_ray for certificates) or the raw iterate (3: u_x,
+// 4: u_y, 5: v_s) of the scaled problem.
 template <typename T>
 __global__ void k_extract(const InstDesc* insts, int inst, int what, int64_t off, int64_t len,
                           double* out) {
@@ -658,17 +649,33 @@ __global__ void k_extract(const InstDesc* insts, int inst, int what, int64_t off
     const double status = sc[SC_STATUS];
     double scale = 1.0;
     gptr<const T> v;
+    gptr<const T> w = nullptr;
+    bool divide = false;
     if (what == 0 || what == 3) v = xvec<T>(d, XU);
     else if (what == 1 || what == 4) v = yvec<T>(d, YU);
     else v = yvec<T>(d, YV);
     if (what <= 2) {
-        if (status == 3.0) scale = (what == 1) ? 1.0 / (-sc[SC_BUY]) : NAN;
-        else if (status == 4.0) scale = (what == 1) ? NAN : 1.0 / (-sc[SC_CUX]);
-        else scale = 1.0 / sc[SC_TAU];
+        double ray = sc[SC_TAU];   // x = x_ray / tau, ...
+        if (status == 3.0) ray = (what == 1) ? -sc[SC_BUY] : NAN;
+        else if (status == 4.0) ray = (what == 1) ? NAN : -sc[SC_CUX];
+        if (what == 0) {          // x_ray = E u_x / sb
+            w = xvec<T>(d, XE);
+            scale = 1.0 / (sc[SC_SB] * ray);
+        } else if (what == 1) {   // y_ray = D u_y / sc
+            w = yvec<T>(d, YD);
+            scale = 1.0 / (sc[SC_SC] * ray);
+        } else {                  // s_ray = v_s / (D sb)
+            w = yvec<T>(d, YD);
+            divide = true;
+            scale = 1.0 / (sc[SC_SB] * ray);
+        }
     }
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
-         i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (double)v[off + i] * scale;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double e = (double)v[off + i];
+        if (w) e = divide ? e / (double)w[off + i] : e * (double)w[off + i];
+        out[i] = e * scale;
+    }
 }
 
 template <typename T>

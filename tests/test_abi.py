@@ -122,3 +122,36 @@ def test_request_bytes_and_server_precision_check():
     assert nb >= 512
     with pytest.raises(P.CgsError):
         P.Server.request_bytes(op, 5, [5], P.BF16)
+
+
+def _equil_cases():
+    import workloads as w
+    from paper_1609_03488_amd.problems import ConeProblem
+    import oracle as o
+    d = w.deconv_instance(300, 31, 4.0, 0.1, 1e-4, 3)
+    yield P.deconv_problem(d["c"], d["b"]), o.deconv_program(d["c"], d["b"])
+    d = w.lasso_instance(40, 70, 0.1, 1e-4, 4)
+    yield P.lasso_problem(d["A"], d["b"], d["lam"]), o.lasso_program(d["A"], d["b"], d["lam"])
+    # two dense blocks in different row ranges, a row no block touches, cones
+    rng = np.random.default_rng(5)
+    A1, A2 = rng.standard_normal((6, 3)), 10.0 * rng.standard_normal((5, 2))
+    op = P.Operator(12, 5).add_dense(0, 0, A1).add_dense(7, 3, A2, scale=0.5)
+    A = np.zeros((12, 5))
+    A[0:6, 0:3] = A1
+    A[7:12, 3:5] = 0.5 * A2
+    b, c = rng.standard_normal(12), rng.standard_normal(5)
+    prog = o.dense_program(A, b, c, 7, [5])
+    prog.blocks = [(0, 6, 0, 3), (7, 5, 3, 2)]      # the blocks the library sees
+    yield ConeProblem(op, 7, [5], b, c, 5), prog
+
+
+def test_library_equilibration_matches_oracle():
+    """Host-side scaling of the library (block Frobenius norms) against the
+    oracle's (squared-operator applies): same groups, D, E and data scales."""
+    import oracle as o
+    for pr, prog in _equil_cases():
+        d, e, sig = pr.op.equilibrate(pr.l, pr.q, pr.b, pr.c)
+        ref = o.equilibrate(prog)
+        np.testing.assert_allclose(d, ref.D, rtol=1e-12)
+        np.testing.assert_allclose(e, ref.E, rtol=1e-12)
+        np.testing.assert_allclose(sig, (ref.sigma_b, ref.sigma_c), rtol=1e-12)

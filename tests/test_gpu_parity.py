@@ -69,26 +69,31 @@ def _abs_bound(prog, v, adj):
                            [v[2 * n] + v[-1]]])
 
 
+@pytest.mark.parametrize("norm", [0, 1], ids=["given", "equilibrated"])
 @pytest.mark.parametrize("prec,mfma", [(P.FP64, 0), (P.FP32, 0), (P.FP32, 1)],
                          ids=["fp64", "fp32-valu", "fp32-mfma"])
 @pytest.mark.parametrize("idx", range(len(CASES)))
-def test_forward_and_adjoint_apply(idx, prec, mfma):
+def test_forward_and_adjoint_apply(idx, prec, mfma, norm):
     """Elementwise: |dev - ref| <= (K + 4) u sum_j |a_ij||v_j|, with u the unit
     roundoff of the working precision and K the number of terms accumulated in
     that precision (convolution taps; the dense block accumulates in FP64).
-    FP32 convolutions run on the vector ALU or on the matrix cores."""
+    FP32 convolutions run on the vector ALU or on the matrix cores.  With
+    equilibration the device applies D A E, the oracle's scaled operator."""
     name, pr, prog = CASES[idx]
-    _say("apply", name, prec, "mfma" if mfma else "valu")
-    s = _solver(pr, prec, conv_mfma=mfma)
+    _say("apply", name, prec, "mfma" if mfma else "valu", "norm" if norm else "given")
+    s = _solver(pr, prec, conv_mfma=mfma, normalize=norm)
     rng = np.random.default_rng(idx)
     z = rng.standard_normal(prog.n)
     y = rng.standard_normal(prog.m)
     az = s.apply(z)
     aty = s.apply(y, transpose=True)
-    ref_az, ref_aty = prog.A(z), prog.AT(y)
+    work, scl = o.prepare(prog, bool(norm))
+    ref_az, ref_aty = work.A(z), work.AT(y)
     u = 2.0 ** -53 if prec == P.FP64 else 2.0 ** -24
     K = prog.data.get("k", 4) + 4
-    bf, ba = _abs_bound(prog, z, False), _abs_bound(prog, y, True)
+    # |D A E| |v| = D (|A| (E |v|))
+    bf = scl.D * _abs_bound(prog, scl.E * z, False)
+    ba = scl.E * _abs_bound(prog, scl.D * y, True)
     assert np.all(np.abs(az - ref_az) <= (K + 4) * u * bf + 1e-300)
     assert np.all(np.abs(aty - ref_aty) <= (K + 4) * u * ba + 1e-300)
     # adjoint identity on the device results
@@ -99,7 +104,7 @@ def test_identity_kernel_conv_is_exact():
     _say("conv k=1")
     b = np.linspace(-1, 1, 2500)
     pr = P.deconv_problem(np.array([1.0]), b)
-    s = _solver(pr, P.FP64)
+    s = _solver(pr, P.FP64, normalize=0)
     z = np.concatenate([np.arange(2500.0), [3.0]])
     out = s.apply(z)
     np.testing.assert_array_equal(out[:2500], -np.arange(2500.0))
@@ -118,7 +123,7 @@ def test_cg_matches_direct_solve(idx, prec):
     r = rng.standard_normal(prog.n)
     tol = 1e-12 if prec == P.FP64 else 1e-6
     z, it = s.normal_solve(r, tol=tol, max_iters=500)
-    ref = prog.factor().solve(r)
+    ref = o.prepare(prog)[0].factor().solve(r)   # I + (D A E)^T (D A E)
     err = np.linalg.norm(z - ref) / np.linalg.norm(ref)
     assert err < (1e-10 if prec == P.FP64 else 2e-5), err
     assert 0 < it < 500
@@ -198,7 +203,9 @@ def test_residuals_match_oracle(idx):
         ux, uy, tau, vs, kap = s.state(0)
         info = s.residuals()[0]
     assert tau > 0.0
-    rp, rd, gap, pobj, dobj = o.scs.residuals(prog, ux, uy, tau, vs)
+    # the state is that of the equilibrated problem; the residuals are the original's
+    x, y, sl = o.equilibrate(prog).unscale(ux, uy, 1.0, vs)
+    rp, rd, gap, pobj, dobj = o.scs.residuals(prog, x, y, tau, sl)
     np.testing.assert_allclose([info["res_pri"], info["res_dual"], info["gap"]], [rp, rd, gap],
                                rtol=1e-9, atol=1e-14)
     np.testing.assert_allclose([info["pobj"], info["dobj"]], [pobj, dobj], rtol=1e-9, atol=1e-12)
@@ -374,7 +381,7 @@ def test_bf16_gemm_apply(B):
     """BF16 operands (RNE) with FP32 accumulation: |dev - ref| <= (2^-8 + K 2^-24) sum |a||v|."""
     _say("bf16 gemm apply", B)
     A, prs, progs = _lasso_batch(300, 700, B, 41)
-    s = _solver(prs[0], P.BF16, batch=B)
+    s = _solver(prs[0], P.BF16, batch=B, normalize=0)
     prog = progs[0]
     rng = np.random.default_rng(B)
     z = rng.standard_normal(prog.n)
@@ -414,7 +421,7 @@ def test_autotune_keeps_results_within_bounds():
     error bounds of the apply tests above."""
     name, pr, prog = CASES[1]
     _say("autotune conv", name)
-    s = _solver(pr, P.FP32)
+    s = _solver(pr, P.FP32, normalize=0)
     ch = s.autotune(reps=3)
     assert ch["conv_mfma"] in (0, 1) and ch["gemm_target_wgs"] == -1
     rng = np.random.default_rng(5)
@@ -423,7 +430,7 @@ def test_autotune_keeps_results_within_bounds():
     assert np.all(np.abs(s.apply(z) - prog.A(z)) <= (K + 4) * u * _abs_bound(prog, z, False))
     _say("autotune gemm")
     A, prs, progs = _lasso_batch(300, 700, 37, 41)
-    s = _solver(prs[0], P.BF16, batch=37)
+    s = _solver(prs[0], P.BF16, batch=37, normalize=0)
     ch = s.autotune(reps=3)
     assert ch["conv_mfma"] == -1 and ch["gemm_target_wgs"] in (128, 256, 512, 1024)
     y = rng.standard_normal(progs[0].m)
