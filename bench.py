@@ -118,17 +118,28 @@ def run_deconv(args, cfg):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        prog = oracle.deconv_program(data["c"], data["b"])
+        # bounded sample: the same family at n_s <= 2^14 (same kernel, density,
+        # noise), factorisation + setup + a few iterations timed; banded
+        # factorisation and solves cost O(n k^2) and O(n k), so the time is
+        # scaled by n / n_s and to the GPU's iteration count
+        n_s = min(n, args.cpu_sample_n)
+        if n_s < n:
+            ds = w.deconv_instance(n_s, k, cfg["sigma"], cfg["density"], cfg["noise_var"], cfg["seed"])
+        else:
+            ds = data
+        prog = oracle.deconv_program(ds["c"], ds["b"])
         t0 = time.perf_counter()
         fac = oracle.prepare(prog)[0].factor()   # of the equilibrated operator
         t_factor = time.perf_counter() - t0
         res = oracle.scs_solve(prog, eps=cfg["eps"], max_iters=args.cpu_iters, check_every=10, fac=fac)
         t_iter = res.solve_s / max(res.iters, 1)
-        t_solve = t_factor + res.setup_s + last["iters"] * t_iter
+        scale = n / n_s
+        t_solve = scale * (t_factor + res.setup_s + last["iters"] * t_iter)
         cpu = {"value": 1.0 / t_solve, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
-               "sample": (f"FP64 banded-Cholesky SCS oracle on the same problem: factorisation "
-                          f"{t_factor:.1f} s + embedding setup {res.setup_s:.1f} s + {res.iters} ADMM "
-                          f"iterations ({t_iter:.2f} s each) timed, extrapolated to the GPU's "
+               "sample": (f"FP64 banded-Cholesky SCS oracle on the same family at n = {n_s} "
+                          f"(k = {k}): factorisation {t_factor:.1f} s + embedding setup "
+                          f"{res.setup_s:.2f} s + {res.iters} ADMM iterations ({t_iter:.3f} s each) "
+                          f"timed; x{scale:g} for n = {n} and extrapolated to the GPU's "
                           f"{last['iters']} iterations -> {t_solve:.0f} s per solve")}
         log("cpu", cpu)
     out = base_record(args, args.steps / elapsed, "solves/s", elapsed,
@@ -372,6 +383,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--cpu-solves", type=int, default=4)
+    ap.add_argument("--cpu-sample-n", type=int, default=1 << 14,
+                    help="signal length of the deconvolution sample the oracle is timed on")
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

@@ -111,14 +111,16 @@ typedef struct {
                               the solver / server qualifies; 0 disables (default 65536) */
     int32_t conv_mfma;     /* 1: FP32 convolutions run on the matrix cores (16x16x4 FP32
                               MFMA over Toeplitz blocks of the taps); 0: vector ALU  */
-    int32_t normalize;     /* 1 (default): iterate on equilibrated data D A E,
-                              sb D b, sc E c, with diagonal D (rows) and E (columns)
-                              constant on every operator block and second-order cone
-                              (Ruiz passes on the blocks' Frobenius norms, then b and
-                              c scaled to the mean row / column norm).  Termination
-                              and returned points are those of the original problem;
-                              the raw state and the diagnostic apply / normal solve
-                              are in the scaled variables.  0: data as given.     */
+    int32_t normalize;     /* data scaling the iteration runs on: 1 (default):
+                              sb b, sc c with sb, sc bringing b and c to the mean row /
+                              column norm of A (A itself, and so the conditioning of
+                              the CG systems, unchanged); 2: first D A E with diagonal
+                              D (rows) and E (columns) constant on every operator
+                              block and second-order cone (20 Ruiz passes on the
+                              blocks' Frobenius norms), then sb D b, sc E c; 0: data
+                              as given.  Termination and returned points are those
+                              of the original problem; the raw state and the
+                              diagnostic apply / normal solve use the scaled data. */
     int32_t reserved[3];
 } cgs_settings;
 
@@ -169,15 +171,15 @@ int cgs_op_add_dense(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64
                      const double* a, int64_t lda, double scale);
 /* Number of blocks and the operator size. */
 int cgs_op_info(const cgs_op* op, int64_t* m, int64_t* n, int64_t* nblocks);
-/* The equilibration a solver with normalize = 1 applies to this operator and
+/* The scaling a solver with normalize = level applies to this operator and
  * cone (host computation, no device work): d (m entries) and e (n entries)
- * receive the row and column scalings D and E, constant on the groups of
- * rows / columns that every block and second-order cone lies in; with b (m)
- * and c (n) given, sigma[2] receives {sigma_b, sigma_c}, the factors of
- * b^ = sigma_b D b and c^ = sigma_c E c.  Any output may be NULL.  The raw
- * solver state is u^ = (sigma_b E^-1 x tau, sigma_c D^-1 y tau, tau) with
- * v^_s = sigma_b D s tau. */
-int cgs_op_equilibrate(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
+ * receive the row and column scalings D and E (all ones below level 2),
+ * constant on the groups of rows / columns that every block and second-order
+ * cone lies in; with b (m) and c (n) given, sigma[2] receives
+ * {sigma_b, sigma_c}, the factors of b^ = sigma_b D b and c^ = sigma_c E c.
+ * Any output may be NULL.  The raw solver state is
+ * u^ = (sigma_b E^-1 x tau, sigma_c D^-1 y tau, tau), v^_s = sigma_b D s tau. */
+int cgs_op_equilibrate(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, int32_t level,
                        const double* b, const double* c, double* d, double* e, double* sigma);
 void cgs_op_destroy(cgs_op* op);
 

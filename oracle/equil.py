@@ -3,7 +3,10 @@
 The paper notes that operator applications alone suffice to precondition a
 problem (Section III, computation graphs); it does not fix a scheme.  The
 reading taken here, and mirrored by the HIP library, is SCS's data
-normalisation restricted to scalings that are constant on the operator's blocks:
+normalisation restricted to scalings that are constant on the operator's blocks,
+in two levels: ``passes = 0`` leaves ``D = E = I`` and only scales ``b`` and
+``c`` (the operator, and so the conditioning of ``I + A^T A`` that conjugate
+gradients see, is unchanged); ``passes = 20`` also balances the blocks:
 
 * Groups.  Rows are partitioned into the coarsest contiguous groups such that
   every nonzero block of ``A`` and every second-order cone lies inside one
@@ -15,7 +18,7 @@ normalisation restricted to scalings that are constant on the operator's blocks:
   ``D_g <- D_g / sqrt(rho_g)`` with ``rho_g`` the root-mean-square row norm of
   ``D A E`` over group ``g``, then ``E_h <- E_h / sqrt(gamma_h)`` with the
   column norms of the row-scaled matrix; the norms are clipped to
-  ``[1e-4, 1e4]``, and a group with zero norm keeps its scale.  20 passes.
+  ``[1e-4, 1e4]``, and a group with zero norm keeps its scale.
 * Data scaling.  ``b^ = sigma_b D b`` and ``c^ = sigma_c E c`` with
   ``sigma_b = mean row norm / max(||D b||, 1e-4)`` and
   ``sigma_c = mean column norm / max(||E c||, 1e-4)`` (means weighted by the
@@ -101,7 +104,7 @@ def group_norms(prog: ConeProgram, rg: np.ndarray, cg: np.ndarray) -> np.ndarray
     return F
 
 
-def equilibrate(prog: ConeProgram) -> Scaling:
+def equilibrate(prog: ConeProgram, passes: int = PASSES) -> Scaling:
     rg, cg = groups(prog)
     F = group_norms(prog, rg, cg)
     R = np.bincount(rg).astype(np.float64)
@@ -115,7 +118,7 @@ def equilibrate(prog: ConeProgram) -> Scaling:
     def col_rms():
         return np.sqrt(E * E * (F.T @ (D * D)) / C)
 
-    for _ in range(PASSES):
+    for _ in range(passes):
         rho = row_rms()
         D = np.where(rho > 0, D / np.sqrt(np.clip(rho, NORM_MIN, NORM_MAX)), D)
         gam = col_rms()

@@ -28,9 +28,10 @@ Iteration (relaxation ``alpha``)::
 ``z = M^{-1} w_xy`` (``z_x = K^{-1}(w_x - A^T w_y)``, ``z_y = w_y + A z_x``),
 ``u~_tau = (w_tau + c^T z_x + b^T z_y) / eta``, ``u~_xy = z - u~_tau g``.
 
-Readings where the paper is silent: the iteration runs on the block-constant
-equilibrated data of ``oracle.equil`` (``normalize=True``, the default) or on
-the data as given, ``alpha = 1.5``, start ``u = v = (0, 0, 1)``; ``v_x`` stays
+Readings where the paper is silent: the iteration runs on the scaled data of
+``oracle.equil`` -- ``normalize=1`` (the default) scales ``b`` and ``c`` only,
+``normalize=2`` also balances the operator's blocks, ``normalize=0`` keeps the
+data as given -- ``alpha = 1.5``, start ``u = v = (0, 0, 1)``; ``v_x`` stays
 0 and is not stored (the ``y``-block of ``v`` is ``s``).  Termination, on the
 unscaled point, uses the relative 2-norm criteria
 ``res_pri = ||A x + s - b|| / (1 + ||b||)``,
@@ -49,7 +50,7 @@ from typing import Callable, Optional
 import numpy as np
 
 from .cones import proj_cone
-from .equil import Scaling, equilibrate, identity_scaling, scaled_program
+from .equil import PASSES, Scaling, equilibrate, identity_scaling, scaled_program
 from .program import ConeProgram, Factor
 
 
@@ -100,10 +101,14 @@ def residuals(prog: ConeProgram, ux, uy, tau, vs):
     return rp, rd, gap, cx, -by
 
 
-def prepare(prog: ConeProgram, normalize: bool = True):
-    """``(working program, scaling)``: the equilibrated program, or ``prog`` itself."""
+def prepare(prog: ConeProgram, normalize: int = 1):
+    """``(working program, scaling)``: the scaled program (``normalize`` 1: data
+    only, 2: blocks and data), or ``prog`` itself (0)."""
+    normalize = int(normalize)
+    if normalize not in (0, 1, 2):
+        raise ValueError("normalize must be 0, 1 or 2")
     if normalize:
-        scl = equilibrate(prog)
+        scl = equilibrate(prog, passes=PASSES if normalize == 2 else 0)
         return scaled_program(prog, scl), scl
     return prog, identity_scaling(prog)
 
@@ -112,7 +117,7 @@ def scs_solve(prog: ConeProgram, eps: float = 1e-8, alpha: float = 1.5,
               max_iters: int = 100_000, check_every: int = 1,
               fac: Optional[Factor] = None, warm: Optional[tuple] = None,
               callback: Optional[Callable] = None,
-              time_limit_s: Optional[float] = None, normalize: bool = True) -> ScsResult:
+              time_limit_s: Optional[float] = None, normalize: int = 1) -> ScsResult:
     """Run the HSDE ADMM iteration to the relative tolerance ``eps``.
 
     ``fac`` factors ``I + A^T A`` of the working (scaled) program.

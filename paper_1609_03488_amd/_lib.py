@@ -75,7 +75,8 @@ _SIGS = {
     "cgs_op_add_conv": (C.c_int, [_P, _I64, _I64, _DP, _I64, _I64, _D]),
     "cgs_op_add_dense": (C.c_int, [_P, _I64, _I64, _I64, _I64, _DP, _I64, _D]),
     "cgs_op_info": (C.c_int, [_P, _I64P, _I64P, _I64P]),
-    "cgs_op_equilibrate": (C.c_int, [_P, C.c_int64, _I64P, C.c_int64, _DP, _DP, _DP, _DP, _DP]),
+    "cgs_op_equilibrate": (C.c_int, [_P, C.c_int64, _I64P, C.c_int64, C.c_int32, _DP, _DP, _DP, _DP,
+                                     _DP]),
     "cgs_op_destroy": (None, [_P]),
     "cgs_settings_default": (None, [C.POINTER(Settings)]),
     "cgs_workspace_bytes": (C.c_int, [_P, _I64, _I64P, _I64, C.POINTER(Settings), _I64,
@@ -189,15 +190,15 @@ class Operator:
         self.kinds.append("dense")
         return self
 
-    def equilibrate(self, l: int, q: Sequence[int], b=None, c=None):
-        """Row / column scalings (D, E) a normalising solver uses for this
-        operator and cone, and (sigma_b, sigma_c) when b and c are given."""
+    def equilibrate(self, l: int, q: Sequence[int], b=None, c=None, level: int = 2):
+        """Row / column scalings (D, E) a solver with normalize = level uses for
+        this operator and cone, and (sigma_b, sigma_c) when b and c are given."""
         qa = np.asarray(list(q), dtype=np.int64)
         d, e = np.empty(self.m), np.empty(self.n)
         sig = np.empty(2)
         bb = None if b is None else _f64(b, self.m)
         cc = None if c is None else _f64(c, self.n)
-        _check(lib().cgs_op_equilibrate(self._h, int(l), qa.ctypes.data_as(_I64P), len(qa),
+        _check(lib().cgs_op_equilibrate(self._h, int(l), qa.ctypes.data_as(_I64P), len(qa), int(level),
                                         None if bb is None else _dp(bb),
                                         None if cc is None else _dp(cc), _dp(d), _dp(e), _dp(sig)))
         return d, e, ((float(sig[0]), float(sig[1])) if bb is not None else None)

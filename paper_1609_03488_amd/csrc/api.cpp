@@ -208,13 +208,14 @@ int cgs_op_info(const cgs_op* op, int64_t* m, int64_t* n, int64_t* nblocks) {
     return CGS_OK;
 }
 
-int cgs_op_equilibrate(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
+int cgs_op_equilibrate(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, int32_t level,
                        const double* b, const double* c, double* d, double* e, double* sigma) {
     if (!op) return fail(CGS_EINVAL, "operator is null");
     CGS_TRY(cgs::validate_cone(op->m, l, q, nq));
+    if (level < 0 || level > 2) return fail(CGS_EINVAL, "level must be 0, 1 or 2");
     if ((b == nullptr) != (c == nullptr)) return fail(CGS_EINVAL, "give both b and c, or neither");
     cgs::Scaling scl;
-    cgs::compute_scaling(*op, l, q, nq, true, &scl);
+    cgs::compute_scaling(*op, l, q, nq, level, &scl);
     std::vector<double> dv((size_t)op->m), ev((size_t)op->n), bh((size_t)op->m), ch((size_t)op->n);
     std::vector<double> zb((size_t)op->m, 0.0), zc((size_t)op->n, 0.0);
     double sb = 1.0, sc = 1.0;
@@ -320,7 +321,7 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
         e.panel_lo = (uint16_t*)p; p += L.panel;
         e.gemm_part = (float*)p; p += L.part;
     }
-    cgs::compute_scaling(*op, l, q, nq, st->normalize != 0, &s->scl);
+    cgs::compute_scaling(*op, l, q, nq, st->normalize, &s->scl);
     CGS_TRY(cgs::op_upload(*op, st->precision, opdata, e.stg, e.stream, &s->opdev, s->scl.blk.data()));
     std::vector<cgs::InstRec> recs((size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
@@ -804,7 +805,7 @@ int cgs_server_submit(cgs_server* sv, const cgs_op* op, int64_t l, const int64_t
     r->t_submit = now_s();
     char* base = sv->arena + off;
     cgs::Scaling scl;
-    cgs::compute_scaling(*op, l, q, nq, e.st.normalize != 0, &scl);
+    cgs::compute_scaling(*op, l, q, nq, e.st.normalize, &scl);
     int rc = cgs::op_upload(*op, e.precision, base + region, e.stg, e.stream, &r->opdev, scl.blk.data());
     if (rc != CGS_OK) {
         arena_free(sv, off, bytes);

@@ -51,7 +51,7 @@ int validate_settings(const cgs_settings* s) {
     if (s->setup_max_iters < 1) return fail(CGS_EINVAL, "setup_max_iters must be >= 1");
     if (s->bf16_phase1_digits < 0 || s->bf16_phase1_digits > 15)
         return fail(CGS_EINVAL, "bf16_phase1_digits must be in [0, 15]");
-    if (s->normalize != 0 && s->normalize != 1) return fail(CGS_EINVAL, "normalize must be 0 or 1");
+    if (s->normalize < 0 || s->normalize > 2) return fail(CGS_EINVAL, "normalize must be 0, 1 or 2");
     return CGS_OK;
 }
 
@@ -122,9 +122,10 @@ int group_of(const std::vector<int64_t>& lo, int64_t i) {
 }
 }  // namespace
 
-void compute_scaling(const cgs_op& op, int64_t l, const int64_t* q, int64_t nq, bool on,
+void compute_scaling(const cgs_op& op, int64_t l, const int64_t* q, int64_t nq, int level,
                      Scaling* out) {
-    constexpr int kPasses = 20;
+    const int kPasses = level >= 2 ? 20 : 0;
+    const bool on = level >= 1;
     constexpr double kMin = 1e-4, kMax = 1e4;
     std::vector<std::pair<int64_t, int64_t>> rows, cols;
     for (const auto& b : op.blocks) {
@@ -591,6 +592,15 @@ void Engine::check() {
 
 // Exact recomputation of the carried products of the CG warm start.
 void Engine::refresh() {
+    if (use_fused) {
+        // instances that run fused steps keep their products in that kernel's
+        // arithmetic (a result must not depend on when the host refreshes)
+        FusedArgs fa{};
+        fa.refresh = 1;
+        fa.kc = fused_kc;
+        launch_fused(prec, T, fa, stream);
+        return;
+    }
     apply(0, YA, XZ, -1, 1.0, G_ADMM);                           // A z
     apply(1, XK, YA, XZ, 1.0, G_ADMM);                           // z + A^T (A z)
 }
@@ -652,7 +662,11 @@ int Engine::fetch_scalars() {
 int Engine::setup() {
     launch_norms(prec, T, G_SETUP, stream);
     apply(1, XH, YB, XC, -1.0, G_SETUP);                          // h = c - A^T b
-    launch_cg_init(prec, T, XG, XR, XP, XQ, XH, 0, 0.0, 0.0, st.setup_tol, st.setup_max_iters,
+    // CG from the current g_x (0 after a reset; the previous operator's
+    // embedding vector when a refined operator restarts the setup)
+    apply(0, YT, XG, -1, 1.0, G_SETUP);                           // A g_x
+    apply(1, XQ, YT, XG, 1.0, G_SETUP);                           // (I + A^T A) g_x
+    launch_cg_init(prec, T, XG, XR, XP, XQ, XH, 1, 0.0, 0.0, st.setup_tol, st.setup_max_iters,
                    G_SETUP, stream);
     int it = 0;
     while (it < st.setup_max_iters) {

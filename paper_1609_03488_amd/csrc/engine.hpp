@@ -84,7 +84,8 @@ struct Scaling {
     double mean_row = 1.0, mean_col = 1.0;
     bool on = false;
 };
-void compute_scaling(const cgs_op& op, int64_t l, const int64_t* q, int64_t nq, bool on,
+// level 0: none; 1: b and c only (D = E = I); 2: Ruiz passes on the blocks, then b and c
+void compute_scaling(const cgs_op& op, int64_t l, const int64_t* q, int64_t nq, int level,
                      Scaling* out);
 // Expanded D (m), E (n), b^ = sb D b, c^ = sc E c; returns {sb, sc}.
 void scale_data(const Scaling& s, int64_t m, int64_t n, const double* b, const double* c,

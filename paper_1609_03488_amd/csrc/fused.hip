@@ -90,6 +90,13 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     const InstDesc d = tb.inst[blockIdx.x];
     gptr<double> sc = scal(d);
     if (!(sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0)) return;
+    if (fa.refresh) {
+        // the same applies as the exact recomputation at a check, so that a
+        // refresh between checks leaves the carried products bitwise unchanged
+        f_apply<T>(tb, d, 0, YA, XZ, -1, 1.0, fa.kc, fsmem);
+        f_apply<T>(tb, d, 1, XK, YA, XZ, 1.0, fa.kc, fsmem);
+        return;
+    }
     const int tid = threadIdx.x;
     const int64_t n = d.n, m = d.m;
     double tau = sc[SC_TAU], kap = sc[SC_KAPPA], ut = sc[SC_UT];

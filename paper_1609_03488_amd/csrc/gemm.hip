@@ -6,9 +6,10 @@
 // vectors.  Three kernels:
 //   pack   : X panel in BF16 (round to nearest even), hi part and the BF16
 //            rounding of the remainder (lo), rows padded to a multiple of 64;
-//   gemm   : split-K MFMA product, FP32 accumulation, FP32 partials per K split;
-//            with `corr` the products X_hi W_lo + X_lo W_hi are added
-//            (operands carried to about 16 significant bits);
+//   gemm   : split-K MFMA product, FP32 accumulation, FP32 partials per K split:
+//            (X_hi + X_lo) W_hi, so that the input keeps about 16 significant
+//            bits and the apply is a fixed linear map (the BF16 matrix); with
+//            `corr` the product X_hi W_lo is added (matrix to about 16 bits);
 //   reduce : out_b[n] += s * sum over K splits (fixed order), gated per instance.
 // The order of the K terms inside a dot product is irrelevant to the result's
 // definition, so each lane feeds the A (panel) and B (W) operands the same
@@ -104,16 +105,16 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_bf16(const uint16_t* __restric
         const bf16x8 bw = __builtin_bit_cast(bf16x8, wh[o]);
         const bf16x8 a0 = __builtin_bit_cast(bf16x8, xh0[o]);
         const bf16x8 a1 = __builtin_bit_cast(bf16x8, xh1[o]);
+        const bf16x8 a0l = __builtin_bit_cast(bf16x8, xl0[o]);
+        const bf16x8 a1l = __builtin_bit_cast(bf16x8, xl1[o]);
         acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bw, acc1, 0, 0, 0);
         if (corr) {
             const bf16x8 bwl = __builtin_bit_cast(bf16x8, wl[o]);
-            const bf16x8 a0l = __builtin_bit_cast(bf16x8, xl0[o]);
-            const bf16x8 a1l = __builtin_bit_cast(bf16x8, xl1[o]);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bwl, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bwl, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bw, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bw, acc1, 0, 0, 0);
         }
     }
     // D layout of a 32x32 MFMA: column = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4

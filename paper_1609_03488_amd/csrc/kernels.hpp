@@ -103,6 +103,7 @@ void launch_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n, hip
 struct FusedArgs {
     int nsteps;
     int check;
+    int refresh;     // 1: only recompute the carried A z and (I + A^T A) z, then return
     double alpha, eps, zeta, rate, floor_;
     int cg_max;
     int max_iters;

@@ -150,8 +150,11 @@ def test_library_equilibration_matches_oracle():
     oracle's (squared-operator applies): same groups, D, E and data scales."""
     import oracle as o
     for pr, prog in _equil_cases():
-        d, e, sig = pr.op.equilibrate(pr.l, pr.q, pr.b, pr.c)
-        ref = o.equilibrate(prog)
-        np.testing.assert_allclose(d, ref.D, rtol=1e-12)
-        np.testing.assert_allclose(e, ref.E, rtol=1e-12)
-        np.testing.assert_allclose(sig, (ref.sigma_b, ref.sigma_c), rtol=1e-12)
+        for level, passes in ((1, 0), (2, 20)):
+            d, e, sig = pr.op.equilibrate(pr.l, pr.q, pr.b, pr.c, level=level)
+            ref = o.equilibrate(prog, passes=passes)
+            np.testing.assert_allclose(d, ref.D, rtol=1e-12)
+            np.testing.assert_allclose(e, ref.E, rtol=1e-12)
+            np.testing.assert_allclose(sig, (ref.sigma_b, ref.sigma_c), rtol=1e-12)
+            if level == 1:
+                assert np.all(d == 1.0) and np.all(e == 1.0)

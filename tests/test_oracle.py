@@ -437,12 +437,12 @@ def test_solution_independent_of_equilibration(family):
     else:
         d = w.lasso_instance(30, 40, 0.1, 1e-4, 12)
         prog = o.lasso_program(d["A"], d["b"], d["lam"])
-        x0 = o.scs_solve(prog, eps=1e-8, normalize=False).x[:40]
+        x0 = o.scs_solve(prog, eps=1e-8, normalize=0).x[:40]
         pol = o.polish_lasso(d["A"], d["b"], d["lam"], x0)
         assert pol["kkt_ok"]
         ref = pol["obj"]
         f = lambda r: o.lasso_objective(d["A"], d["b"], d["lam"], r.x[:40])
-    for norm in (True, False):
+    for norm in (0, 1, 2):
         r = o.scs_solve(prog, eps=1e-9, normalize=norm, max_iters=200_000)
         assert r.status == "solved"
         assert abs(f(r) - ref) <= 1e-7 * (1 + ref), (norm, f(r), ref)
