@@ -106,9 +106,13 @@ typedef struct {
                               (+2, capped at cg_max_iters); 0: always cg_max_iters.
                               A server always uses 0 (results independent of the mix) */
     int32_t fused_max;     /* instances with n + m <= fused_max run whole ADMM steps in
-                              one workgroup each (one launch per check interval, CG
-                              loop inside the kernel); applies when every instance of
-                              the solver / server qualifies; 0 disables (default 65536) */
+                              one workgroup each (one launch per check interval for
+                              all of them, CG loop inside the kernel); larger ones
+                              take one launch per kernel spread over the chip.  The
+                              path depends on an instance's own size only; 0
+                              disables (default 16384: one workgroup beats the
+                              launch overheads of a lone small instance, and a
+                              crowd of them fills the chip)                        */
     int32_t conv_mfma;     /* 1: FP32 convolutions run on the matrix cores (16x16x4 FP32
                               MFMA over Toeplitz blocks of the taps); 0: vector ALU  */
     int32_t normalize;     /* data scaling the iteration runs on: 1 (default):

@@ -57,7 +57,8 @@ enum Scal : int {
     SC_CX, SC_BY,                              // c^T x, b^T y at the last check
     SC_RP, SC_RD, SC_GAP,                      // residuals at the last check
     SC_ACTIVE,                                 // 1 while the instance runs
-    SC_PHASE,                                  // 0: setup pending, 1: iterating
+    SC_PHASE,                                  // 0: setup pending, 1: iterating (one launch
+                                               // per kernel), 2: iterating (fused steps)
     SC_CGACT,                                  // 1 while CG of the instance runs
     SC_CGIT,                                   // CG iterations in the current solve
     SC_CGTOT,                                  // CG iterations since set_data
@@ -84,7 +85,8 @@ enum Gate : int {
     G_ADMM = 3,       // active and iterating
     G_ADMM_CG = 4,    // ... and CG running
     G_CHECK = 5,      // active and iterating (termination test)
-    G_ANY_CG = 6      // CG running, whatever the phase (diagnostic solves)
+    G_ANY_CG = 6,     // CG running, whatever the phase (diagnostic solves)
+    G_CHECK_ANY = 7   // active and iterating on either path (diagnostic residuals)
 };
 
 // ---------------------------------------------------------------- tables
@@ -99,6 +101,8 @@ struct InstDesc {
     int32_t id0, id1;    // identity-block range
     int32_t cb0, cb1;    // convolution-block range (Tables::cblk)
     int32_t db0, db1;    // dense-block range (Tables::dblk)
+    int32_t fused;       // 1: whole ADMM steps run in one workgroup (k_fused)
+    int32_t pad_;
 };
 
 // A tile of an X or Y vector: `len` elements from instance-local `start`.

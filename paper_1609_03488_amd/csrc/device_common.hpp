@@ -37,6 +37,7 @@ DEVI bool gate_ok(gptr<const double> sc, int gate) {
         case G_CHECK: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0;
         case G_ADMM_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0 && sc[SC_CGACT] != 0.0;
         case G_ANY_CG: return sc[SC_CGACT] != 0.0;
+        case G_CHECK_ANY: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] >= 1.0;
         default: return false;
     }
 }

@@ -469,6 +469,12 @@ int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_double
 int Engine::build(const std::vector<InstRec>& r) {
     recs = r;
     build_image(recs, precision, im);
+    // each instance's path depends on its own size only (never on the mix)
+    n_fused = n_multi = 0;
+    for (InstDesc& d : im.inst) {
+        d.fused = (st.fused_max > 0 && !use_gemm && d.n + d.m <= (int64_t)st.fused_max) ? 1 : 0;
+        (d.fused ? n_fused : n_multi) += 1;
+    }
     const size_t tb = image_table_bytes(im), wb = image_work_bytes(im);
     if (tb > tab_cap || tb > tab_host_cap || wb > work_cap || (int)im.inst.size() > scal_host_cap)
         return fail(CGS_ENOMEM, "tile tables need %zu + %zu bytes (have %zu + %zu)", tb, wb, tab_cap, work_cap);
@@ -516,13 +522,6 @@ int Engine::build(const std::vector<InstRec>& r) {
     T.ny_tiles = (int)im.yt.size();
     T.nseg = (int)im.seg.size();
     T.ninst = (int)im.inst.size();
-    // fused path when every instance is small (and no batched GEMM is in use)
-    use_fused = 0;
-    if (st.fused_max > 0 && !use_gemm && !im.inst.empty()) {
-        bool small = true;
-        for (const InstDesc& d : im.inst) small = small && (d.n + d.m <= (int64_t)st.fused_max);
-        use_fused = small ? 1 : 0;
-    }
     fused_kc = (int)conv_r(precision);
     for (const ConvBlock& cb : im.cblk) fused_kc = std::max<int>(fused_kc, (int)std::min(kcmax, cb.kpad));
     CGS_HIP(hipStreamSynchronize(stream));
@@ -551,8 +550,8 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
     if (use_gemm) {
         // every instance shares the dense blocks: one MFMA GEMM per block
         for (const DenseBlock& db : recs[0].op->dense)
-            launch_gemm_apply(inst_dev, T.ninst, db, adj, out, in, sigma, gate, gemm_corr, panel_hi,
-                              panel_lo, gemm_part, gemm_target, stream);
+            launch_gemm_apply(inst_dev, T.ninst, db, adj, out, in, sigma, gate, gemm_corr, panel,
+                              panel_stride, gemm_part, gemm_target, stream);
     } else {
         for (const auto& d : adj ? da : df) launch_gemv(prec, T, d, adj, out, in, sigma, gate, stream);
     }
@@ -583,26 +582,30 @@ void Engine::admm_step() {
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
 }
 
-void Engine::check() {
-    apply(0, YT, XU, -1, 1.0, G_CHECK);                          // A u_x
-    apply(1, XT, YU, -1, 1.0, G_CHECK);                          // A^T u_y
-    launch_resid(prec, T, st.eps, st.max_iters, stream);
-    refresh();
+void Engine::check(int gate) {
+    apply(0, YT, XU, -1, 1.0, gate);                             // A u_x
+    apply(1, XT, YU, -1, 1.0, gate);                             // A^T u_y
+    launch_resid(prec, T, st.eps, st.max_iters, gate, stream);
+    if (gate == G_CHECK) {
+        apply(0, YA, XZ, -1, 1.0, G_ADMM);                       // exact A z
+        apply(1, XK, YA, XZ, 1.0, G_ADMM);                       // and z + A^T A z
+    }
 }
 
 // Exact recomputation of the carried products of the CG warm start.
 void Engine::refresh() {
-    if (use_fused) {
+    if (n_fused) {
         // instances that run fused steps keep their products in that kernel's
         // arithmetic (a result must not depend on when the host refreshes)
         FusedArgs fa{};
         fa.refresh = 1;
         fa.kc = fused_kc;
         launch_fused(prec, T, fa, stream);
-        return;
     }
-    apply(0, YA, XZ, -1, 1.0, G_ADMM);                           // A z
-    apply(1, XK, YA, XZ, 1.0, G_ADMM);                           // z + A^T (A z)
+    if (n_multi) {
+        apply(0, YA, XZ, -1, 1.0, G_ADMM);                       // A z
+        apply(1, XK, YA, XZ, 1.0, G_ADMM);                       // z + A^T (A z)
+    }
 }
 
 void Engine::fused_steps(int nsteps, int check) {
@@ -621,8 +624,8 @@ void Engine::fused_steps(int nsteps, int check) {
 }
 
 int Engine::round(int nsteps) {
-    if (use_fused) {
-        fused_steps(nsteps, 1);
+    if (n_fused) fused_steps(nsteps, 1);
+    if (!n_multi) {
         CGS_HIP(hipGetLastError());
         return CGS_OK;
     }

@@ -158,14 +158,15 @@ class Engine {
     std::vector<ConvLaunch> cf, ca;
     std::vector<DenseLaunch> df, da;
     int cg_launch = 1;
-    // fused path: one workgroup per instance runs whole steps (small instances)
-    int use_fused = 0;
+    // fused path: one workgroup per instance runs whole steps (instances with
+    // n + m <= fused_max); the others take one launch per kernel
+    int n_fused = 0, n_multi = 0;
     int fused_kc = 8;
     // batched BF16 MFMA path for dense blocks shared by every instance
     int use_gemm = 0;
     int gemm_corr = 0;           // 1: add the refinement products (hi x lo)
-    uint16_t* panel_hi = nullptr;
-    uint16_t* panel_lo = nullptr;
+    uint16_t* panel = nullptr;   // three BF16 panels (hi, mid, lo) of panel_stride elements
+    size_t panel_stride = 0;
     float* gemm_part = nullptr;
     int gemm_target = 512;       // GEMM workgroups aimed for (autotuned)
 
@@ -186,7 +187,7 @@ class Engine {
     void cg_iter(int z, int gate, int cg_max, int track);
     void admm_step();
     void fused_steps(int nsteps, int check);
-    void check();
+    void check(int gate = G_CHECK);
     void refresh();
     void adapt_cg();
     // ---- host loops

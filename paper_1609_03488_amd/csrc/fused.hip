@@ -89,7 +89,7 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     __shared__ double sh[FNT / 64];
     const InstDesc d = tb.inst[blockIdx.x];
     gptr<double> sc = scal(d);
-    if (!(sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0)) return;
+    if (!(sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 2.0)) return;
     if (fa.refresh) {
         // the same applies as the exact recomputation at a check, so that a
         // refresh between checks leaves the carried products bitwise unchanged

@@ -4,12 +4,14 @@
 // multiple of 16 with zeros) the apply out_b += s * W x_b of every instance is
 // the product  C = X W^T  with X the B x K panel of the instances' input
 // vectors.  Three kernels:
-//   pack   : X panel in BF16 (round to nearest even), hi part and the BF16
-//            rounding of the remainder (lo), rows padded to a multiple of 64;
+//   pack   : X as three BF16 panels (round to nearest even): hi, the BF16
+//            rounding of the remainder (mid) and of what is left (lo), so that
+//            hi + mid + lo carries the FP32 input to about 24 bits; rows padded
+//            to a multiple of 64;
 //   gemm   : split-K MFMA product, FP32 accumulation, FP32 partials per K split:
-//            (X_hi + X_lo) W_hi, so that the input keeps about 16 significant
-//            bits and the apply is a fixed linear map (the BF16 matrix); with
-//            `corr` the product X_hi W_lo is added (matrix to about 16 bits);
+//            (X_hi + X_mid + X_lo) W_hi, a fixed linear map (the BF16 matrix) of
+//            the FP32 input; with `corr` the products (X_hi + X_mid) W_lo are
+//            added (matrix to about 16 bits);
 //   reduce : out_b[n] += s * sum over K splits (fixed order), gated per instance.
 // The order of the K terms inside a dot product is irrelevant to the result's
 // definition, so each lane feeds the A (panel) and B (W) operands the same
@@ -50,7 +52,7 @@ DEVI gptr<T> yvec_g(const InstDesc& d, int k) {
 // (X when !adj, Y when adj) starting at `off`, K valid entries.
 __global__ __launch_bounds__(256) void k_gemm_pack(const InstDesc* insts, int ninst, int adj, int in,
                                                     int64_t off, int64_t K, int64_t kpad, int mpad,
-                                                    uint16_t* hi, uint16_t* lo) {
+                                                    uint16_t* hi, uint16_t* mid, uint16_t* lo) {
     const int b = blockIdx.y;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= kpad) return;
@@ -61,8 +63,11 @@ __global__ __launch_bounds__(256) void k_gemm_pack(const InstDesc* insts, int ni
         v = src[off + k];
     }
     const uint16_t h = f32_to_bf16_rne(v);
+    const float r1 = v - bf16_to_f32(h);           // exact in FP32
+    const uint16_t md = f32_to_bf16_rne(r1);
     hi[(int64_t)b * kpad + k] = h;
-    lo[(int64_t)b * kpad + k] = f32_to_bf16_rne(v - bf16_to_f32(h));
+    mid[(int64_t)b * kpad + k] = md;
+    lo[(int64_t)b * kpad + k] = f32_to_bf16_rne(r1 - bf16_to_f32(md));
     (void)mpad;
 }
 
@@ -77,6 +82,7 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_bf16(const uint16_t* __restric
                                                        const uint16_t* __restrict__ w_lo,
                                                        int64_t N, int64_t kpad,
                                                        const uint16_t* __restrict__ x_hi,
+                                                       const uint16_t* __restrict__ x_mid,
                                                        const uint16_t* __restrict__ x_lo,
                                                        int ksteps_per_split, int corr,
                                                        float* __restrict__ part, int64_t npad,
@@ -97,6 +103,8 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_bf16(const uint16_t* __restric
     const u16x8* wl = reinterpret_cast<const u16x8*>(w_lo + wn * kpad) + half;
     const u16x8* xh0 = reinterpret_cast<const u16x8*>(x_hi + (int64_t)(m0 + row) * kpad) + half;
     const u16x8* xh1 = reinterpret_cast<const u16x8*>(x_hi + (int64_t)(m0 + 32 + row) * kpad) + half;
+    const u16x8* xm0 = reinterpret_cast<const u16x8*>(x_mid + (int64_t)(m0 + row) * kpad) + half;
+    const u16x8* xm1 = reinterpret_cast<const u16x8*>(x_mid + (int64_t)(m0 + 32 + row) * kpad) + half;
     const u16x8* xl0 = reinterpret_cast<const u16x8*>(x_lo + (int64_t)(m0 + row) * kpad) + half;
     const u16x8* xl1 = reinterpret_cast<const u16x8*>(x_lo + (int64_t)(m0 + 32 + row) * kpad) + half;
     f32x16 acc0 = {}, acc1 = {};
@@ -105,17 +113,24 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_bf16(const uint16_t* __restric
         const bf16x8 bw = __builtin_bit_cast(bf16x8, wh[o]);
         const bf16x8 a0 = __builtin_bit_cast(bf16x8, xh0[o]);
         const bf16x8 a1 = __builtin_bit_cast(bf16x8, xh1[o]);
+        const bf16x8 a0m = __builtin_bit_cast(bf16x8, xm0[o]);
+        const bf16x8 a1m = __builtin_bit_cast(bf16x8, xm1[o]);
         const bf16x8 a0l = __builtin_bit_cast(bf16x8, xl0[o]);
         const bf16x8 a1l = __builtin_bit_cast(bf16x8, xl1[o]);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw, acc1, 0, 0, 0);
+        // smallest terms first
         acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bw, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bw, acc1, 0, 0, 0);
         if (corr) {
             const bf16x8 bwl = __builtin_bit_cast(bf16x8, wl[o]);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0m, bwl, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1m, bwl, acc1, 0, 0, 0);
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bwl, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bwl, acc1, 0, 0, 0);
         }
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0m, bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1m, bw, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw, acc1, 0, 0, 0);
     }
     // D layout of a 32x32 MFMA: column = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4
     const int64_t col = n0 + row;
@@ -148,6 +163,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(const InstDesc* insts, int 
         case G_CHECK: on = sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0; break;
         case G_ADMM_CG: on = sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0 && sc[SC_CGACT] != 0.0; break;
         case G_ANY_CG: on = sc[SC_CGACT] != 0.0; break;
+        case G_CHECK_ANY: on = sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] >= 1.0; break;
         default: on = false;
     }
     if (!on) return;
@@ -179,8 +195,11 @@ GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst, int target_wgs) {
 size_t gemm_part_bytes(const GemmPlan& g) { return (size_t)g.nsplit * g.mpad * g.npad * sizeof(float); }
 
 void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
-                       double sigma, int gate, int corr, uint16_t* panel_hi, uint16_t* panel_lo,
+                       double sigma, int gate, int corr, uint16_t* panel, size_t panel_stride,
                        float* part, int target_wgs, hipStream_t st) {
+    uint16_t* panel_hi = panel;
+    uint16_t* panel_mid = panel + panel_stride;
+    uint16_t* panel_lo = panel + 2 * panel_stride;
     const int64_t N = adj ? db.cols : db.rows;        // outputs
     const int64_t K = adj ? db.rows : db.cols;        // inputs
     const int64_t kpad = adj ? db.ldt : db.ld;
@@ -190,10 +209,11 @@ void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, i
     const int64_t off_out = adj ? db.col0 : db.row0;
     const GemmPlan g = gemm_plan(N, kpad, ninst, target_wgs);
     dim3 pg((unsigned)((kpad + 255) / 256), (unsigned)g.mpad);
-    k_gemm_pack<<<pg, 256, 0, st>>>(insts, ninst, adj, in, off_in, K, kpad, g.mpad, panel_hi, panel_lo);
+    k_gemm_pack<<<pg, 256, 0, st>>>(insts, ninst, adj, in, off_in, K, kpad, g.mpad, panel_hi, panel_mid,
+                                    panel_lo);
     dim3 gg((unsigned)g.ntiles, (unsigned)g.nsplit, (unsigned)(g.mpad / GEMM_TM));
-    k_gemm_bf16<<<gg, GEMM_NT, 0, st>>>(w_hi, w_lo, N, kpad, panel_hi, panel_lo, g.ksteps_per_split, corr,
-                                        part, g.npad, g.mpad);
+    k_gemm_bf16<<<gg, GEMM_NT, 0, st>>>(w_hi, w_lo, N, kpad, panel_hi, panel_mid, panel_lo,
+                                        g.ksteps_per_split, corr, part, g.npad, g.mpad);
     dim3 rg((unsigned)((N + 255) / 256), (unsigned)ninst);
     k_gemm_reduce<<<rg, 256, 0, st>>>(insts, ninst, adj, out, off_out, N, part, g.nsplit, g.npad, g.mpad,
                                       sigma * db.scale, gate);

@@ -358,12 +358,12 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
 // the original problem's units: the row sums are divided by D, the column sums
 // by E (sums listed at check_outcome).  YT holds A u_x and XT holds A^T u_y on entry.
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max_iters) {
+__global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max_iters, int gate) {
     __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
-    if (!gate_ok(sc, G_CHECK)) return;
+    if (!gate_ok(sc, gate)) return;
     const double tau = sc[SC_TAU];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
             break;
         case FIN_ETA:
             sc[SC_ETA] = 1.0 + x0 + y0;
-            sc[SC_PHASE] = 1.0;
+            sc[SC_PHASE] = d.fused ? 2.0 : 1.0;
             sc[SC_CGACT] = 0.0;
             break;
         default:
@@ -816,9 +816,9 @@ void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st) {
 void launch_project(int prec, const Tables& t, double alpha, hipStream_t st) {
     CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
 }
-void launch_resid(int prec, const Tables& t, double eps, int max_iters, hipStream_t st) {
-    CGS_DISPATCH(prec, k_resid, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, eps, max_iters);
-    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_RESID, G_CHECK, FinArgs{eps, 0, 0, max_iters, 0});
+void launch_resid(int prec, const Tables& t, double eps, int max_iters, int gate, hipStream_t st) {
+    CGS_DISPATCH(prec, k_resid, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, eps, max_iters, gate);
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_RESID, gate, FinArgs{eps, 0, 0, max_iters, 0});
 }
 void launch_reset(int prec, const Tables& t, int only, hipStream_t st) {
     CGS_DISPATCH(prec, k_reset, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, only);

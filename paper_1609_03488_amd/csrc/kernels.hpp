@@ -64,7 +64,7 @@ void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st);
 // relaxation, projection onto K, dual update of every X/Y entry
 void launch_project(int prec, const Tables& t, double alpha, hipStream_t st);
 // termination quantities from A u_x (in YT) and A^T u_y (in XT)
-void launch_resid(int prec, const Tables& t, double eps, int max_iters, hipStream_t st);
+void launch_resid(int prec, const Tables& t, double eps, int max_iters, int gate, hipStream_t st);
 
 // ---- setup
 // u = v = (0,0,1), z = g = 0, scalars cleared; only >= 0 restricts to one instance
@@ -128,7 +128,7 @@ size_t gemm_part_bytes(const GemmPlan& g);
 // W in BF16 (plus refinement products when corr); panel_hi/lo hold
 // mpad x kpad BF16 values, part the split-K partials.
 void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
-                       double sigma, int gate, int corr, uint16_t* panel_hi, uint16_t* panel_lo,
+                       double sigma, int gate, int corr, uint16_t* panel, size_t panel_stride,
                        float* part, int target_wgs, hipStream_t st);
 
 }  // namespace cgs

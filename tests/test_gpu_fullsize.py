@@ -84,7 +84,8 @@ def test_lasso_5000x10000_fp32_against_exact():
     _say(cfg["name"])
     d = w.make_lasso(cfg)
     pr = P.lasso_problem(d["A"], d["b"], d["lam"])
-    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10)
+    # a 1e-4 stop leaves the objective ~1e-4 off (1.2e-4 measured); 1e-5 for the bar
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"] / 10, check_every=10)
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=torch.cuda.Stream())
     s.set_data(0, pr.b, pr.c)
     info = s.solve()[0]
@@ -105,7 +106,8 @@ def test_lasso_batch64_bf16_against_exact():
     d = w.make_lasso_batch(cfg)
     B = cfg["batch"]
     prs = [P.lasso_problem(d["A"], d["b"][i], d["lam"][i]) for i in range(B)]
-    st = P.Settings.make(precision=P.BF16, eps=cfg["eps"], check_every=10)
+    # stops at eps / 10 so that the objective lands within 1e-4 of the optimum
+    st = P.Settings.make(precision=P.BF16, eps=cfg["eps"] / 10, check_every=10)
     s = P.Solver(prs[0].op, prs[0].l, prs[0].q, st, batch=B, stream=torch.cuda.Stream())
     for i, pr in enumerate(prs):
         s.set_data(i, pr.b, pr.c)
@@ -116,6 +118,6 @@ def test_lasso_batch64_bf16_against_exact():
         x, y, sl = s.solution(i)
         prog = o.lasso_program(d["A"], d["b"][i], d["lam"][i])
         rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
-        assert max(rp, rd, gap) <= 1.5e-4, (i, rp, rd, gap)
+        assert max(rp, rd, gap) <= 1e-4, (i, rp, rd, gap)
         f = o.lasso_objective(d["A"], d["b"][i], d["lam"][i], x[:cfg["n"]])
         assert abs(f - ref["objective"]) / ref["objective"] <= 1e-4, (i, f, ref["objective"])

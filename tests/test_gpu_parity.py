@@ -226,11 +226,14 @@ def _objective(prog, x):
 
 @pytest.mark.parametrize("fused", [0, 65536], ids=["multikernel", "fused"])
 @pytest.mark.parametrize("idx,prec,eps", [(0, P.FP64, 1e-4), (0, P.FP32, 1e-4),
-                                           (1, P.FP64, 1e-6), (1, P.FP32, 1e-4)])
+                                           (1, P.FP64, 1e-6), (1, P.FP32, 1e-5)])
 def test_solve_matches_oracle(idx, prec, eps, fused):
     """Same method, same tolerance: the natural objective of the GPU solution is
     within 1e-4 (relative) of the oracle's, and the GPU point's residuals,
-    recomputed in FP64, meet the tolerance."""
+    recomputed in FP64, meet the tolerance.  At a 1e-4 stop the lasso's
+    objective is itself only ~1e-4 accurate (a 1.3e-4 spread was measured
+    between the FP32 and FP64 stopping points), so its FP32 case stops at 1e-5;
+    the deconvolution's FP32 and FP64 trajectories stay together at 1e-4."""
     name, pr, prog = ITER_CASES[idx]
     _say("solve", name, prec, eps, fused)
     s = _solver(pr, prec, eps=eps, check_every=10, fused_max=fused)
@@ -318,7 +321,9 @@ def test_server_result_same_alone_and_in_mix():
     reqs = [w.deconv_instance(n, k, k / 7.0, 0.05, 1e-4, 4000 + n) for n, k in
             ((1500, 41), (3700, 101), (900, 11), (2600, 65))]
     prs = [P.deconv_problem(d["c"], d["b"]) for d in reqs]
-    st = P.Settings.make(precision=P.FP32, eps=1e-4, check_every=10)
+    # fused_max 8000: the (3700, 101) request runs one launch per kernel, the
+    # others whole steps in one workgroup; both paths share the rounds
+    st = P.Settings.make(precision=P.FP32, eps=1e-4, check_every=10, fused_max=8000)
     alone = []
     for pr in prs:
         sv = P.Server(64 << 20, 8, st)
@@ -400,11 +405,19 @@ def test_bf16_gemm_apply(B):
     assert np.abs(az - prog.A(z)).max() > 1e-6 * np.abs(prog.A(z)).max()
 
 
+BF16_EPS = 1e-5   # two-phase BF16 solves stop at eps / 10 (objective bar: 1e-4)
+
+
 def test_bf16_batch_solve_matches_oracle():
+    """Each instance's residuals (recomputed in FP64) are <= 1e-4 and its
+    objective is within 1e-4 of the optimum (the oracle at 1e-6).  The relative
+    criteria scale with 1 + ||b|| while the objective can be much smaller (here
+    ~2.5 against ||b|| ~ 25), and a point at a 2.5e-5 residual was measured
+    1.06e-4 off in objective, so the batch stops at 1e-5."""
     _say("bf16 batch solve")
     B = 12
     A, prs, progs = _lasso_batch(250, 600, B, 43)
-    s = _solver(prs[0], P.BF16, batch=B, eps=1e-4, check_every=10)
+    s = _solver(prs[0], P.BF16, batch=B, eps=BF16_EPS, check_every=10)
     for i, pr in enumerate(prs):
         s.set_data(i, pr.b, pr.c)
     infos = s.solve()
@@ -412,8 +425,8 @@ def test_bf16_batch_solve_matches_oracle():
         assert infos[i]["status"] == P.SOLVED, infos[i]
         x, y, sl = s.solution(i)
         rp, rd, gap, _, _ = o.scs.residuals(progs[i], x, y, 1.0, sl)
-        assert max(rp, rd, gap) <= 1.5e-4, (i, rp, rd, gap)
-        ref = o.scs_solve(progs[i], eps=1e-4, check_every=10)
+        assert max(rp, rd, gap) <= 1e-4, (i, rp, rd, gap)
+        ref = o.scs_solve(progs[i], eps=1e-6, check_every=10)
         f, fr = _objective(progs[i], x), _objective(progs[i], ref.x)
         assert abs(f - fr) / abs(fr) <= 1e-4, (i, f, fr)
 
