@@ -154,7 +154,9 @@ def run_deconv(args, cfg):
         "status": last["status_name"], "max_iters_cap": args.max_iters,
         "roofline": {"bound": "mfma" if mfma else "alu", "achieved": achieved,
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": measured_traffic("k_conv_mfma") if mfma else None,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": ("k_conv_mfma (FP32 matrix-core convolution" if mfma else
                                 "k_conv<float> (direct convolution") + " A and its adjoint A^T)",
                      "flop_per_launch": {"A": flop_fwd, "AT": flop_adj},
@@ -162,6 +164,29 @@ def run_deconv(args, cfg):
         "cpu_baseline": cpu, "verify": verify,
     })
     return out
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch (mean over the directions) of `kernel` from the
+    counter record under profiles/, or None when there is none or the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        rec = json.load(open(path))[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    per = [1024.0 * (rec["fetch_kib"][d] * rec["fetch_scale"] + rec["write_kib"][d] * rec["write_scale"])
+           for d in rec["fetch_kib"]]
+    return sum(per) / len(per)
 
 
 # ---------------------------------------------------------------- dense lasso (single)
@@ -175,7 +200,7 @@ def run_lasso(args, cfg):
     m, n = cfg["m"], cfg["n"]
     pr = P.lasso_problem(data["A"], data["b"], data["lam"])
     stream = torch.cuda.Stream()
-    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10, normalize=args.normalize, normalize=args.normalize)
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10, normalize=args.normalize)
     if args.max_iters:
         st.max_iters = args.max_iters
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
