@@ -103,7 +103,7 @@ typedef struct {
                               state to eps with a fresh setup solve (default 3)       */
     int32_t cg_adaptive;   /* 1: CG launches per step follow the most CG iterations any
                               instance used in a step of the previous check interval
-                              (+2, capped at cg_max_iters); 0: always cg_max_iters.
+                              (+1, capped at cg_max_iters); 0: always cg_max_iters.
                               A server always uses 0 (results independent of the mix) */
     int32_t fused_max;     /* instances with n + m <= fused_max run whole ADMM steps in
                               one workgroup each (one launch per check interval for

@@ -387,7 +387,7 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
         if (kernel <= 1) {
             // A u_x into the scratch Y vector, A^T u_y into the scratch X vector
             for (const auto& c : cl)
-                e.conv(c, kernel, kernel ? cgs::XT : cgs::YT, kernel ? cgs::YU : cgs::XU, 1.0, cgs::G_ALL),
+                e.conv(c, kernel, kernel ? cgs::XT : cgs::YT, kernel ? cgs::YU : cgs::XU, -1, 1.0, cgs::G_ALL),
                     ++launches;
         } else if (kernel <= 3) {
             const int adj = kernel == 3;
@@ -693,7 +693,7 @@ int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, 
     int done = 0;
     while (done < max_iters) {
         const int nb = std::min(8, max_iters - done);
-        for (int j = 0; j < nb; ++j) e.cg_iter(cgs::XZ, cgs::G_ANY_CG, max_iters, 0);
+        for (int j = 0; j < nb; ++j) e.cg_iter(cgs::XZ, cgs::G_ANY_CG, max_iters, 0, done + j);
         done += nb;
         CGS_TRY(e.fetch_scalars());
         if (e.scalars(0)[cgs::SC_CGACT] == 0.0) break;

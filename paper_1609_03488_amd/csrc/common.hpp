@@ -69,6 +69,8 @@ enum Scal : int {
     SC_CGMAX,                                  // most CG iterations of a step since the last check
     SC_CGMAXLAST,                              // ... over the previous check interval
     SC_SB, SC_SC,                              // data scales: b^ = sb D b, c^ = sc E c
+    SC_RR2,                                    // CG ||r||^2, second slot: iteration i reads
+                                               // slot i % 2 (SC_RR, SC_RR2), writes the other
     NSC_USED
 };
 constexpr int NSC = 32;      // doubles reserved per instance (256 bytes)
@@ -134,6 +136,12 @@ struct ConvBlock {       // full convolution of n_in inputs with k taps
     const void* w_fwd;   // taps reversed (correlation order for A x), kpad entries
     const void* w_adj;   // taps in order (correlation order for A^T y), kpad entries
     double scale;
+    // bit 0 (A x) / bit 1 (A^T y): no other convolution or dense block writes
+    // into this block's output range, so the convolution writes the final
+    // value there (base + identity blocks + its own sum) and the separate
+    // initialisation pass skips the range
+    int32_t own;
+    int32_t pad_;
 };
 
 struct ConvTile {        // CONV_TILE outputs starting at block-local `start`

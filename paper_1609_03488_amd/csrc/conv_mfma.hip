@@ -35,8 +35,14 @@ DEVI int cm_nj(int kc) { return (kc + 14) / 16 + 1; }          // J blocks of a 
 DEVI int cm_stride(int nj) { const int q = nj + 31; return q | 1; }   // odd row stride
 
 __global__ __launch_bounds__(CM_NT) void k_conv_mfma(Tables tb, ConvLaunch cl, int adj, int out, int in,
-                                                     double sigma, int gate) {
+                                                     int base, double sigma, int gate) {
     extern __shared__ __align__(16) unsigned char cm_smem[];
+    if ((int)blockIdx.x >= cl.ntiles) {   // initialisation tiles riding on the launch
+        const VecTile it = cl.init[blockIdx.x - cl.ntiles];
+        const InstDesc di = tb.inst[it.inst];
+        if (gate_ok(scal(di), gate)) init_tile<float>(tb, di, it, adj, out, in, base, sigma);
+        return;
+    }
     const ConvTile tl = cl.tiles[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
@@ -130,10 +136,21 @@ __global__ __launch_bounds__(CM_NT) void k_conv_mfma(Tables tb, ConvLaunch cl, i
     // D[a][b]: a = 4 (lane / 16) + v, b = lane % 16 -> output o0 + 16 b + a
     const double s = sigma * cb.scale;
     const int64_t o0 = ot + CM_SUB * sub + 16 * col + 4 * g;
+    if ((cb.own >> adj) & 1) {   // this block alone writes its outputs: final values
+        const int64_t g0 = adj ? cb.col0 : cb.row0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int64_t oi = o0 + v;
-        if (oi < n_out) o[oi] = (float)((double)o[oi] + s * (double)(acc0[v] + acc1[v]));
+        for (int v = 0; v < 4; ++v) {
+            const int64_t oi = o0 + v;
+            if (oi < n_out)
+                o[oi] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + oi) +
+                                s * (double)(acc0[v] + acc1[v]));
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t oi = o0 + v;
+            if (oi < n_out) o[oi] = (float)((double)o[oi] + s * (double)(acc0[v] + acc1[v]));
+        }
     }
 }
 
@@ -143,10 +160,11 @@ size_t conv_mfma_smem_bytes(int kc) {
     return (size_t)(16 * S + 16 * nj + 32) * sizeof(float);
 }
 
-void launch_conv_mfma(const Tables& t, const ConvLaunch& c, int adj, int out, int in, double sigma,
-                      int gate, hipStream_t st) {
-    if (c.ntiles <= 0) return;
-    k_conv_mfma<<<c.ntiles, CM_NT, conv_mfma_smem_bytes(c.kc), st>>>(t, c, adj, out, in, sigma, gate);
+void launch_conv_mfma(const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base,
+                      double sigma, int gate, hipStream_t st) {
+    const int grid = c.ntiles + c.ninit;
+    if (grid <= 0) return;
+    k_conv_mfma<<<grid, CM_NT, conv_mfma_smem_bytes(c.kc), st>>>(t, c, adj, out, in, base, sigma, gate);
 }
 
 }  // namespace cgs

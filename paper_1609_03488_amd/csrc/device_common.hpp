@@ -73,6 +73,19 @@ DEVI double sum_parts(const double* part, int t0, int t1, int j, double* sh) {
     return block_sum<NT>(s, sh);
 }
 
+// Fixed-order sum of the instance's X-tile partials (slot j) of the previous
+// kernel, returned to every thread: each workgroup of a consumer kernel
+// recomputes the same value, so no separate one-workgroup kernel is needed.
+DEVI double inst_xsum(const Tables& tb, const InstDesc& d, int j, double* sh) {
+    const double s = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, j, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) sh[0] = s;
+    __syncthreads();
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
 // Tile of a kernel that walks the X tiles and then the Y tiles.
 struct XYTile {
     VecTile t;
@@ -148,7 +161,6 @@ DEVI void conv_step(T (&acc)[R], const T (&lo)[R], const T (&hi)[R], const T (&t
     }
 }
 
-// relaxed point minus v for a Y entry
 // Termination test from the six sums of a check on the scaled iterate
 // (u^, v^) with A^ = D A E, b^ = sb D b, c^ = sc E c:
 //   y0 = ||(A^ u^_x + v^_s - tau b^) / D||^2   y1 = ||(A^ u^_x + v^_s) / D||^2   y2 = b^T u^_y
@@ -196,6 +208,65 @@ DEVI CheckOut check_outcome(gptr<const double> sc, double tau, double kap, doubl
     return o;
 }
 
+// The part of an apply's output element g (index in the output vector) that
+// does not come from convolution or dense blocks: base[g] (base >= 0) plus the
+// identity blocks of the instance that cover g.
+template <typename T>
+DEVI double owned_init(const InstDesc& d, const IdBlock* ids, int adj, int out, int in, int base,
+                       double sigma, int64_t g) {
+    (void)out;
+    gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
+    double v = base >= 0 ? (double)(adj ? xvec<T>(d, base) : yvec<T>(d, base))[g] : 0.0;
+    for (int b = d.id0; b < d.id1; ++b) {
+        const IdBlock ib = ids[b];
+        const int64_t r0 = adj ? ib.col0 : ib.row0;
+        const int64_t c0 = adj ? ib.row0 : ib.col0;
+        if (g >= r0 && g < r0 + ib.len) v += sigma * ib.scale * (double)src[g - r0 + c0];
+    }
+    return v;
+}
+
+// Initialisation of an apply's output tile: base plus identity blocks, for the
+// elements that no owning convolution writes (the tile's ends are trimmed
+// against owned ranges; an owned range inside the tile is skipped element by
+// element).  Convolution and dense blocks that do not own their range then
+// accumulate into these values.
+template <typename T>
+DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int adj, int out, int in,
+                    int base, double sigma) {
+    gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
+    gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
+    gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
+    int64_t lo = tl.start, hi = tl.start + tl.len;
+    int64_t olo[4], ohi[4];
+    int nown = 0;
+    for (int b = d.cb0; b < d.cb1 && nown < 4; ++b) {
+        const ConvBlock cb = tb.cblk[b];
+        if (!((cb.own >> adj) & 1)) continue;
+        olo[nown] = adj ? cb.col0 : cb.row0;
+        ohi[nown] = olo[nown] + (adj ? cb.n_in : cb.n_in + cb.k - 1);
+        ++nown;
+    }
+    for (int j = 0; j < nown; ++j) {
+        if (olo[j] <= lo && ohi[j] > lo) lo = ohi[j] < hi ? ohi[j] : hi;
+        if (olo[j] < hi && ohi[j] >= hi) hi = olo[j] > lo ? olo[j] : lo;
+    }
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        bool owned = false;
+        for (int j = 0; j < nown; ++j) owned = owned || (i >= olo[j] && i < ohi[j]);
+        if (owned) continue;
+        double v = bs ? (double)bs[i] : 0.0;
+        for (int b = d.id0; b < d.id1; ++b) {
+            const IdBlock ib = tb.ids[b];
+            const int64_t r0 = adj ? ib.col0 : ib.row0;
+            const int64_t c0 = adj ? ib.row0 : ib.col0;
+            if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
+        }
+        o[i] = (T)v;
+    }
+}
+
+// relaxed point minus v for a Y entry
 template <typename T>
 DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, double& ubar) {
     const double uy = (double)yvec<T>(d, YU)[i];
@@ -210,7 +281,8 @@ DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, 
 // workgroup; starts and ends with a workgroup barrier.
 template <typename T, int NT>
 DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, int in, double sigma,
-                    int64_t ot, int KC, unsigned char* smem) {
+                    int64_t ot, int KC, unsigned char* smem, const IdBlock* ids = nullptr,
+                    int base = -1) {
     constexpr int R = ConvCfg<T>::R, TILE = NT * R;
     T* win = reinterpret_cast<T*>(smem);        // TILE + KC + 2R entries
     T* taps = win + TILE + KC + 2 * R;          // KC entries
@@ -291,10 +363,20 @@ DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, in
         }
     }
     const double s = sigma * cb.scale;
+    if (ids && (cb.own >> adj) & 1) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t oi = ot + (int64_t)tid * R + r;
-        if (oi < n_out) o[oi] = (T)((double)o[oi] + s * (double)acc[r]);
+        for (int r = 0; r < R; ++r) {
+            const int64_t oi = ot + (int64_t)tid * R + r;
+            if (oi < n_out) o[oi] = (T)(owned_init<T>(d, ids, adj, out, in, base, sigma,
+                                                      (adj ? cb.col0 : cb.row0) + oi) +
+                                        s * (double)acc[r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t oi = ot + (int64_t)tid * R + r;
+            if (oi < n_out) o[oi] = (T)((double)o[oi] + s * (double)acc[r]);
+        }
     }
     __syncthreads();
 }

@@ -232,6 +232,25 @@ void op_dev_shape(const cgs_op& op, int precision, OpDev* out, const double* mul
             out->dense.push_back(db);
         }
     }
+    // a convolution owns its output range in a direction when no other
+    // convolution or dense block writes into it (identity blocks may)
+    auto overlap = [](int64_t a0, int64_t a1, int64_t b0, int64_t b1) { return a0 < b1 && b0 < a1; };
+    for (size_t i = 0; i < out->convs.size(); ++i) {
+        ConvBlock& c = out->convs[i];
+        const int64_t r0 = c.row0, r1 = c.row0 + c.n_in + c.k - 1, c0 = c.col0, c1 = c.col0 + c.n_in;
+        bool fwd = true, adj = true;
+        for (size_t j = 0; j < out->convs.size(); ++j) {
+            if (j == i) continue;
+            const ConvBlock& o = out->convs[j];
+            if (overlap(r0, r1, o.row0, o.row0 + o.n_in + o.k - 1)) fwd = false;
+            if (overlap(c0, c1, o.col0, o.col0 + o.n_in)) adj = false;
+        }
+        for (const DenseBlock& o : out->dense) {
+            if (overlap(r0, r1, o.row0, o.row0 + o.rows)) fwd = false;
+            if (overlap(c0, c1, o.col0, o.col0 + o.cols)) adj = false;
+        }
+        c.own = (fwd ? 1 : 0) | (adj ? 2 : 0);
+    }
 }
 
 int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hipStream_t st,
@@ -413,6 +432,7 @@ size_t image_table_bytes(const TableImage& im) {
     for (const auto& v : im.cadj) t += vbytes(v);
     for (const auto& v : im.dfwd) t += vbytes(v);
     for (const auto& v : im.dadj) t += vbytes(v);
+    t += vbytes(im.xt) + vbytes(im.yt);   // initialisation tiles folded into convolution launches
     return t + 256;
 }
 
@@ -452,7 +472,7 @@ void Engine::adapt_cg() {
         const double* sc = scalars(i);
         if (sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0) need = std::max(need, sc[SC_CGMAXLAST]);
     }
-    cg_launch = std::max(2, std::min(st.cg_max_iters, (int)need + 2));
+    cg_launch = std::max(1, std::min(st.cg_max_iters, (int)need + 1));
 }
 
 int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles) {
@@ -504,9 +524,38 @@ int Engine::build(const std::vector<InstRec>& r) {
         return (int)kc;
     };
     for (const auto& v : im.cfwd)
-        cf.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(), slot_kc(v)});
+        cf.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(),
+                                slot_kc(v), nullptr, 0});
     for (const auto& v : im.cadj)
-        ca.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(), slot_kc(v)});
+        ca.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(),
+                                slot_kc(v), nullptr, 0});
+    // When every convolution owns its output range in a direction, the output
+    // initialisation rides on the first convolution launch as extra
+    // workgroups (one launch fewer per apply); tiles wholly inside an owned
+    // range need no initialisation at all.
+    for (int adj = 0; adj < 2; ++adj) {
+        std::vector<ConvLaunch>& cl = adj ? ca : cf;
+        fold_init[adj] = 0;
+        if (cl.empty()) continue;
+        bool all = true;
+        for (const ConvBlock& cb : im.cblk) all = all && ((cb.own >> adj) & 1);
+        if (!all) continue;
+        std::vector<VecTile> init;
+        for (const VecTile& t : adj ? im.xt : im.yt) {
+            const InstDesc& d = im.inst[t.inst];
+            bool covered = false;
+            for (int b = d.cb0; b < d.cb1 && !covered; ++b) {
+                const ConvBlock& cb = im.cblk[b];
+                const int64_t lo = adj ? cb.col0 : cb.row0;
+                const int64_t hi = lo + (adj ? cb.n_in : cb.n_in + cb.k - 1);
+                covered = lo <= t.start && t.start + t.len <= hi;
+            }
+            if (!covered) init.push_back(t);
+        }
+        cl[0].init = (const VecTile*)put(init.data(), init.size() * sizeof(VecTile));
+        cl[0].ninit = (int)init.size();
+        fold_init[adj] = 1;
+    }
     for (const auto& v : im.dfwd) df.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
     for (const auto& v : im.dadj) da.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
     if (off > tab_cap) return fail(CGS_ENOMEM, "table overflow");
@@ -539,14 +588,14 @@ char* Engine::yptr(int i, int kind) const {
 }
 
 // Convolution tiles: matrix cores for FP32 (unless disabled), VALU otherwise.
-void Engine::conv(const ConvLaunch& c, int adj, int out, int in, double sigma, int gate) {
-    if (prec == 1 && st.conv_mfma) launch_conv_mfma(T, c, adj, out, in, sigma, gate, stream);
-    else launch_conv(prec, T, c, adj, out, in, sigma, gate, stream);
+void Engine::conv(const ConvLaunch& c, int adj, int out, int in, int base, double sigma, int gate) {
+    if (prec == 1 && st.conv_mfma) launch_conv_mfma(T, c, adj, out, in, base, sigma, gate, stream);
+    else launch_conv(prec, T, c, adj, out, in, base, sigma, gate, stream);
 }
 
 void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
-    launch_apply_init(prec, T, adj, out, in, base, sigma, gate, stream);
-    for (const auto& c : adj ? ca : cf) conv(c, adj, out, in, sigma, gate);
+    if (!fold_init[adj]) launch_apply_init(prec, T, adj, out, in, base, sigma, gate, stream);
+    for (const auto& c : adj ? ca : cf) conv(c, adj, out, in, base, sigma, gate);
     if (use_gemm) {
         // every instance shares the dense blocks: one MFMA GEMM per block
         for (const DenseBlock& db : recs[0].op->dense)
@@ -559,12 +608,12 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
 
 // One CG iteration of the Section IV-B listing on (I + A^T A):
 // q = p + A^T (A p); alpha = rr/<p,q>; z += alpha p; r -= alpha q; beta; p = r + beta p.
-void Engine::cg_iter(int z, int gate, int cg_max, int track) {
+void Engine::cg_iter(int z, int gate, int cg_max, int track, int it) {
     apply(0, YT, XP, -1, 1.0, gate);
     apply(1, XQ, YT, XP, 1.0, gate);
     launch_cg_dot(prec, T, XP, XQ, gate, stream);
-    launch_cg_update(prec, T, z, XR, XP, XQ, cg_max, gate, track, stream);
-    launch_cg_dir(prec, T, XR, XP, gate, stream);
+    launch_cg_update(prec, T, z, XR, XP, XQ, it, gate, track, stream);
+    launch_cg_dir(prec, T, XR, XP, it, cg_max, gate, stream);
 }
 
 // One ADMM step of the homogeneous self-dual embedding.  The CG warm start z
@@ -572,11 +621,11 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track) {
 // recomputed exactly at every termination check, so a step applies the
 // operator 1 + 2 * (CG iterations) times.
 void Engine::admm_step() {
-    launch_wy(prec, T, G_ADMM, stream);                        // w_y = u_y + v_s
+    // w_y = u_y + v_s was written by the previous step's projection (or refresh)
     apply(1, XH, YW, XU, -1.0, G_ADMM);                          // h = u_x - A^T w_y
     launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
                    st.cg_max_iters, G_ADMM, stream);             // r = h - K z
-    for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1);
+    for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i);
     launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; u~_tau, tau, kappa
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
@@ -603,6 +652,7 @@ void Engine::refresh() {
         launch_fused(prec, T, fa, stream);
     }
     if (n_multi) {
+        launch_wy(prec, T, G_ADMM, stream);                      // w_y = u_y + v_s
         apply(0, YA, XZ, -1, 1.0, G_ADMM);                       // A z
         apply(1, XK, YA, XZ, 1.0, G_ADMM);                       // z + A^T (A z)
     }
@@ -674,7 +724,7 @@ int Engine::setup() {
     int it = 0;
     while (it < st.setup_max_iters) {
         const int nb = std::min(8, st.setup_max_iters - it);
-        for (int j = 0; j < nb; ++j) cg_iter(XG, G_SETUP_CG, st.setup_max_iters, 0);
+        for (int j = 0; j < nb; ++j) cg_iter(XG, G_SETUP_CG, st.setup_max_iters, 0, it + j);
         it += nb;
         CGS_TRY(fetch_scalars());
         bool any = false;

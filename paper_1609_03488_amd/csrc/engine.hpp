@@ -156,6 +156,7 @@ class Engine {
     InstDesc* inst_dev = nullptr;
     double* gather_dev = nullptr;
     std::vector<ConvLaunch> cf, ca;
+    int fold_init[2] = {0, 0};   // output initialisation rides on the first convolution launch
     std::vector<DenseLaunch> df, da;
     int cg_launch = 1;
     // fused path: one workgroup per instance runs whole steps (instances with
@@ -183,8 +184,8 @@ class Engine {
 
     // ---- device work (enqueue only)
     void apply(int adj, int out, int in, int base, double sigma, int gate);
-    void conv(const ConvLaunch& c, int adj, int out, int in, double sigma, int gate);
-    void cg_iter(int z, int gate, int cg_max, int track);
+    void conv(const ConvLaunch& c, int adj, int out, int in, int base, double sigma, int gate);
+    void cg_iter(int z, int gate, int cg_max, int track, int it);
     void admm_step();
     void fused_steps(int nsteps, int check);
     void check(int gate = G_CHECK);

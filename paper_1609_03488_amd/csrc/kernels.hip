@@ -31,31 +31,24 @@ __global__ __launch_bounds__(VEC_NT) void k_apply_init(Tables tb, int adj, int o
     const VecTile tl = adj ? tb.xt[blockIdx.x] : tb.yt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
-    gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
-    gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
-    gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
-    const int64_t lo = tl.start, hi = tl.start + tl.len;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-        double v = bs ? (double)bs[i] : 0.0;
-        for (int b = d.id0; b < d.id1; ++b) {
-            const IdBlock ib = tb.ids[b];
-            const int64_t r0 = adj ? ib.col0 : ib.row0;
-            const int64_t c0 = adj ? ib.row0 : ib.col0;
-            if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
-        }
-        o[i] = (T)v;
-    }
+    init_tile<T>(tb, d, tl, adj, out, in, base, sigma);
 }
 
 template <typename T>
 __global__ __launch_bounds__(CONV_NT) void k_conv(Tables tb, ConvLaunch cl, int adj, int out, int in,
-                                                  double sigma, int gate) {
+                                                  int base, double sigma, int gate) {
     extern __shared__ __align__(16) unsigned char conv_smem[];
+    if ((int)blockIdx.x >= cl.ntiles) {   // initialisation tiles riding on the launch
+        const VecTile it = cl.init[blockIdx.x - cl.ntiles];
+        const InstDesc di = tb.inst[it.inst];
+        if (gate_ok(scal(di), gate)) init_tile<T>(tb, di, it, adj, out, in, base, sigma);
+        return;
+    }
     const ConvTile tl = cl.tiles[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
     const ConvBlock cb = cl.blocks[tl.blk];
-    conv_tile<T, CONV_NT>(d, cb, adj, out, in, sigma, tl.start, cl.kc, conv_smem);
+    conv_tile<T, CONV_NT>(d, cb, adj, out, in, sigma, tl.start, cl.kc, conv_smem, tb.ids, base);
 }
 
 size_t conv_smem_bytes(int prec, int kc) {
@@ -182,21 +175,29 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
         s0 = fma((double)pv[i], (double)qv[i], s0);
     s0 = block_sum<VEC_NT>(s0, sh);
-    if (threadIdx.x == 0) tb.xpart[4 * (int64_t)blockIdx.x] = s0;
+    if (threadIdx.x == 0) tb.xpart[4 * (int64_t)blockIdx.x] = s0;   // slot 0
 }
 
-// z += alpha p; r -= alpha q; partial ||r||^2; with `track`, the carried
-// products follow z:  K z += alpha q (X tiles) and A z += alpha A p (Y tiles,
-// A p sits in YT).
+// z += alpha p, r -= alpha q (and the carried K z, A z when tracking), with
+// alpha = ||r||^2 / <p, q> recomputed by every workgroup from k_cg_dot's
+// partials; ||r'||^2 partials go to slot 1.  CG iteration `slot` = it % 2.
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q,
-                                                      int cg_max, int gate, int track) {
+__global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q, int slot,
+                                                      int gate, int track) {
     __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
-    const double al = sc[SC_ALPHA];
+    const double pq = inst_xsum(tb, d, 0, sh);
+    const double al = sc[slot ? SC_RR2 : SC_RR] / pq;
+    const bool ok = pq > 0.0 && std::isfinite(al);
+    if (!xt.is_y && xt.index == d.xt0 && threadIdx.x == 0) {
+        sc[SC_PQ] = pq;
+        sc[SC_ALPHA] = ok ? al : 0.0;
+        if (!ok) sc[SC_CGACT] = 0.0;   // every workgroup reaches the same decision
+    }
+    if (!ok) return;
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     double s0 = 0.0;
     if (!xt.is_y) {
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
             s0 = fma((double)ri, (double)ri, s0);
         }
         s0 = block_sum<VEC_NT>(s0, sh);
-        if (threadIdx.x == 0) tb.xpart[4 * (int64_t)xt.index] = s0;
+        if (threadIdx.x == 0) tb.xpart[4 * (int64_t)xt.index + 1] = s0;
     } else {
         gptr<T> az = yvec<T>(d, YA);
         gptr<const T> ap = yvec<T>(d, YT);
@@ -223,20 +224,38 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
     }
 }
 
+// beta = ||r'||^2 / ||r||^2 and the stop test, recomputed by every workgroup
+// from k_cg_update's partials; p = r + beta p while CG goes on.  The first
+// tile's workgroup records the new ||r||^2 (in the other slot, which no
+// workgroup of this kernel reads), the counters and the run flag.
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_cg_dir(Tables tb, int r, int p, int gate) {
+__global__ __launch_bounds__(VEC_NT) void k_cg_dir(Tables tb, int r, int p, int slot, int it,
+                                                   int cg_max, int gate) {
+    __shared__ double sh[VEC_NT / 64];
     const VecTile tl = tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
-    gptr<const double> sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
-    const double be = sc[SC_BETA];
+    const double rr = inst_xsum(tb, d, 1, sh);
+    const double prev = sc[slot ? SC_RR2 : SC_RR];
+    const double be = prev > 0.0 ? rr / prev : 0.0;
+    const bool more = std::isfinite(rr) && sqrt(rr) > sc[SC_CGTOL] && it + 1 < cg_max;
+    if ((int)blockIdx.x == d.xt0 && threadIdx.x == 0) {
+        sc[slot ? SC_RR : SC_RR2] = rr;
+        sc[SC_BETA] = be;
+        sc[SC_CGIT] += 1.0;
+        sc[SC_CGTOT] += 1.0;
+        if (sc[SC_CGIT] > sc[SC_CGMAX]) sc[SC_CGMAX] = sc[SC_CGIT];
+        if (gate == G_SETUP_CG) sc[SC_SETUPIT] += 1.0;
+        sc[SC_CGACT] = more ? 1.0 : 0.0;
+    }
+    if (!more) return;
     gptr<const T> rv = xvec<T>(d, r);
     gptr<T> pv = xvec<T>(d, p);
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
         pv[i] = (T)fma(be, (double)pv[i], (double)rv[i]);
 }
 
-// ---------------------------------------------------------------- ADMM step
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_wy(Tables tb, int gate) {
     const VecTile tl = tb.yt[blockIdx.x];
@@ -320,13 +339,16 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
     }
     gptr<T> uy = yvec<T>(d, YU);
     gptr<T> vs = yvec<T>(d, YV);
+    gptr<T> wy = yvec<T>(d, YW);
     if (xt.t.seg < 0) {
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             double ub;
             const double pv = ybar_minus_v<T>(d, i, ut, alpha, ub);
             const double pr = pv > 0.0 ? pv : 0.0;
-            uy[i] = (T)pr;
-            vs[i] = (T)(pr - pv);
+            const T u = (T)pr, v = (T)(pr - pv);
+            uy[i] = u;
+            vs[i] = v;
+            wy[i] = (T)((double)u + (double)v);
         }
         return;
     }
@@ -349,8 +371,10 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         if (mode == 0) pr = pv;
         else if (mode == 1) pr = 0.0;
         else pr = (i == sg.start) ? a : (a / nz) * pv;
-        uy[i] = (T)pr;
-        vs[i] = (T)(pr - pv);
+        const T u = (T)pr, v = (T)(pr - pv);
+        uy[i] = u;
+        vs[i] = v;
+        wy[i] = (T)((double)u + (double)v);   // w_y of the next step
     }
 }
 
@@ -412,8 +436,6 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
 // tile order and finishes the scalar work of the method.
 enum FinMode : int {
     FIN_CG_INIT = 0,   // rr = ||r||^2, ||h||; CG tolerance and start flag
-    FIN_CG_DOT,        // alpha = rr / <p, q>
-    FIN_CG_UPDATE,     // rr', beta, stop test
     FIN_TAU,           // u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta; tau, kappa
     FIN_RESID,         // residuals, gap, certificates, status
     FIN_NORMS,         // ||b||, ||c||
@@ -459,30 +481,6 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
             sc[SC_CGTOL] = tol;
             sc[SC_CGIT] = 0.0;
             sc[SC_CGACT] = (cg_max > 0 && sqrt(x0) > tol && std::isfinite(x0)) ? 1.0 : 0.0;
-            break;
-        }
-        case FIN_CG_DOT: {
-            sc[SC_PQ] = x0;
-            const double al = sc[SC_RR] / x0;
-            if (x0 > 0.0 && std::isfinite(al)) {
-                sc[SC_ALPHA] = al;
-            } else {
-                sc[SC_ALPHA] = 0.0;
-                sc[SC_CGACT] = 0.0;
-            }
-            break;
-        }
-        case FIN_CG_UPDATE: {
-            const int cg_max = fa.i0;
-            const double prev = sc[SC_RR];
-            sc[SC_BETA] = prev > 0.0 ? x0 / prev : 0.0;
-            sc[SC_RR] = x0;
-            sc[SC_CGIT] += 1.0;
-            sc[SC_CGTOT] += 1.0;
-            if (sc[SC_CGIT] > sc[SC_CGMAX]) sc[SC_CGMAX] = sc[SC_CGIT];
-            if (gate == G_SETUP_CG) sc[SC_SETUPIT] += 1.0;
-            const bool more = std::isfinite(x0) && sqrt(x0) > sc[SC_CGTOL] && sc[SC_CGIT] < (double)cg_max;
-            sc[SC_CGACT] = more ? 1.0 : 0.0;
             break;
         }
         case FIN_TAU: {
@@ -770,12 +768,13 @@ void launch_apply_init(int prec, const Tables& t, int adj, int out, int in, int 
     CGS_DISPATCH(prec, k_apply_init, adj ? t.nx_tiles : t.ny_tiles, VEC_NT, st, t, adj, out, in,
                  base, sigma, gate);
 }
-void launch_conv(int prec, const Tables& t, const ConvLaunch& c, int adj, int out, int in,
+void launch_conv(int prec, const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base,
                  double sigma, int gate, hipStream_t st) {
-    if (c.ntiles <= 0) return;
+    const int grid = c.ntiles + c.ninit;
+    if (grid <= 0) return;
     const size_t lds = conv_smem_bytes(prec, c.kc);
-    if (prec == 0) k_conv<double><<<c.ntiles, CONV_NT, lds, st>>>(t, c, adj, out, in, sigma, gate);
-    else k_conv<float><<<c.ntiles, CONV_NT, lds, st>>>(t, c, adj, out, in, sigma, gate);
+    if (prec == 0) k_conv<double><<<grid, CONV_NT, lds, st>>>(t, c, adj, out, in, base, sigma, gate);
+    else k_conv<float><<<grid, CONV_NT, lds, st>>>(t, c, adj, out, in, base, sigma, gate);
 }
 void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int out, int in,
                  double sigma, int gate, hipStream_t st) {
@@ -789,16 +788,14 @@ void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h
 }
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, gate);
-    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_DOT, gate, FinArgs{0, 0, 0, 0, 0});
 }
-void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int cg_max,
-                      int gate, int track, hipStream_t st) {
+void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int gate,
+                      int track, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_update, t.nx_tiles + (track ? t.ny_tiles : 0), VEC_NT, st, t, z, r, p, q,
-                 cg_max, gate, track);
-    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_UPDATE, gate, FinArgs{0, 0, 0, cg_max, 0});
+                 it & 1, gate, track);
 }
-void launch_cg_dir(int prec, const Tables& t, int r, int p, int gate, hipStream_t st) {
-    CGS_DISPATCH(prec, k_cg_dir, t.nx_tiles, VEC_NT, st, t, r, p, gate);
+void launch_cg_dir(int prec, const Tables& t, int r, int p, int it, int cg_max, int gate, hipStream_t st) {
+    CGS_DISPATCH(prec, k_cg_dir, t.nx_tiles, VEC_NT, st, t, r, p, it & 1, it, cg_max, gate);
 }
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_wy, t.ny_tiles, VEC_NT, st, t, gate);

@@ -15,6 +15,11 @@ struct ConvLaunch {
     const ConvBlock* blocks;
     int ntiles;
     int kc;          // taps per LDS staging pass: min(max kpad of the launch, CONV_KC_MAX)
+    // output-initialisation tiles run by workgroups ntiles.. of the same launch
+    // (only when every convolution owns its output range in this direction, so
+    // that the two kinds of workgroups write disjoint elements)
+    const VecTile* init;
+    int ninit;
 };
 // dynamic LDS bytes of the convolution kernel for a staging pass of kc taps
 size_t conv_smem_bytes(int prec, int kc);
@@ -29,10 +34,11 @@ struct DenseLaunch {
 void launch_apply_init(int prec, const Tables& t, int adj, int out, int in, int base,
                        double sigma, int gate, hipStream_t st);
 // out += sigma * scale * conv(in) for every conv tile (adj selects A or A^T).
-void launch_conv(int prec, const Tables& t, const ConvLaunch& c, int adj, int out, int in,
+void launch_conv(int prec, const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base,
                  double sigma, int gate, hipStream_t st);
 // FP32 only: the same convolution tiles on the matrix cores (conv_mfma.hip)
-void launch_conv_mfma(const Tables& t, const ConvLaunch& c, int adj, int out, int in, double sigma,
+void launch_conv_mfma(const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base,
+                      double sigma,
                       int gate, hipStream_t st);
 size_t conv_mfma_smem_bytes(int kc);
 // out += sigma * scale * a (or a^T) * in for every dense tile.
@@ -44,14 +50,15 @@ void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int o
 //       tol = ||h|| * max(floor, zeta / (k+1)^rate), CG active iff ||r|| > tol.
 void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h, int have_q,
                     double zeta, double rate, double floor, int cg_max, int gate, hipStream_t st);
-// alpha = rr / <p, q>
+// partials of <p, q>
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int gate, hipStream_t st);
-// z += alpha p; r -= alpha q; rr' = ||r||^2; beta = rr'/rr; stop test
+// alpha = rr / <p, q>; z += alpha p; r -= alpha q; partials of ||r||^2
 // track = 1: also K z += alpha q and A z += alpha (A p) (carried products)
-void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int cg_max,
-                      int gate, int track, hipStream_t st);
-// p = r + beta p
-void launch_cg_dir(int prec, const Tables& t, int r, int p, int gate, hipStream_t st);
+// `it`: CG iteration of the current loop (0-based; selects the rr slot)
+void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int gate,
+                      int track, hipStream_t st);
+// rr' , beta, stop test (it + 1 < cg_max); p = r + beta p
+void launch_cg_dir(int prec, const Tables& t, int r, int p, int it, int cg_max, int gate, hipStream_t st);
 
 // ---- ADMM step pieces (Section V-B: subspace projection, then cone projection)
 // w_y = u_y + v_s

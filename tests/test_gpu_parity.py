@@ -474,3 +474,30 @@ def test_solve_with_block_equilibration_matches_oracle(idx, prec, eps, fused):
     ref = o.scs_solve(prog, eps=eps, check_every=10, normalize=2)
     f, fr = _objective(prog, x), _objective(prog, ref.x)
     assert abs(f - fr) / abs(fr) <= 1e-4, (f, fr)
+
+
+@pytest.mark.parametrize("mfma", [0, 1], ids=["valu", "mfma"])
+def test_conv_output_ownership_mixed(mfma):
+    """Two convolutions writing the same rows (neither owns them in A x; each
+    owns its columns in A^T y, shared with an identity block) and one that owns
+    its rows: every apply against the explicit matrix."""
+    _say("conv ownership", mfma)
+    rng = np.random.default_rng(9)
+    c1, c2, c3 = rng.standard_normal(33), rng.standard_normal(17), rng.standard_normal(9)
+    n1, n2, n3 = 1500, 1516, 700
+    m = n1 + 33 - 1 + (n3 + 9 - 1)
+    n = n1 + n2 + n3
+    op = (P.Operator(m, n).add_conv(0, 0, c1, n1, 0.5).add_conv(0, n1, c2, n2, -1.5)
+          .add_identity(3, 10, 40, 2.0).add_conv(n1 + 32, n1 + n2, c3, n3, 1.0))
+    from oracle.program import conv_matrix
+    A = np.zeros((m, n))
+    A[0:n1 + 32, 0:n1] += 0.5 * conv_matrix(c1, n1)
+    A[0:n2 + 16, n1:n1 + n2] += -1.5 * conv_matrix(c2, n2)
+    A[3:43, 10:50] += 2.0 * np.eye(40)
+    A[n1 + 32:, n1 + n2:] += conv_matrix(c3, n3)
+    s = P.Solver(op, m, [], P.Settings.make(precision=P.FP32, conv_mfma=mfma, normalize=0))
+    x, y = rng.standard_normal(n), rng.standard_normal(m)
+    u = 2.0 ** -24
+    ax, aty = s.apply(x), s.apply(y, transpose=True)
+    assert np.all(np.abs(ax - A @ x) <= 50 * u * (np.abs(A) @ np.abs(x)) + 1e-30)
+    assert np.all(np.abs(aty - A.T @ y) <= 50 * u * (np.abs(A).T @ np.abs(y)) + 1e-30)
