@@ -147,7 +147,7 @@ def run_deconv(args, cfg):
                       "f32" if prec == P.FP32 else "f64",
                       {"workload": cfg["name"], "n": n, "kernel_taps": k, "sigma": cfg["sigma"],
                        "eps": cfg["eps"], "variables": n + 1, "constraints": 2 * n + k,
-                       "scalars": "f64"})
+                       "normalize": args.normalize, "scalars": "f64"})
     out.update({
         "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed,
@@ -234,7 +234,7 @@ def run_lasso(args, cfg):
         log("cpu", cpu)
     out = base_record(args, args.steps / elapsed, "solves/s", elapsed, "f32",
                       {"workload": cfg["name"], "m": m, "n": n, "eps": cfg["eps"],
-                       "variables": 2 * n + 1, "constraints": 2 * n + m + 2, "scalars": "f64"})
+                       "variables": 2 * n + 1, "constraints": 2 * n + m + 2, "normalize": args.normalize, "scalars": "f64"})
     out.update({
         "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed, "status": last["status_name"],
@@ -395,7 +395,7 @@ def run_serve(args, cfg):
         log("cpu", cpu)
     out = base_record(args, res["solves_per_s"], "solves/s", res["wall_s"], "f32",
                       {"workload": cfg["name"], "requests": len(trace), "rate_per_s": cfg["rate"],
-                       "eps": cfg["eps"], "scalars": "f64"})
+                       "eps": cfg["eps"], "normalize": args.normalize, "scalars": "f64"})
     out.update({
         "p50_latency_s": res["p50_s"], "p99_latency_s": res["p99_s"], "completed": res["completed"],
         "solved": res["solved"], "mean_admm_iters": res["mean_iters"],
@@ -418,8 +418,10 @@ def main():
                     help="signal length of the deconvolution sample the oracle is timed on")
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--normalize", type=int, default=1, choices=(0, 1, 2),
-                    help="data scaling level of the solver (and of the oracle baseline)")
+    ap.add_argument("--normalize", type=int, default=None, choices=(0, 1, 2),
+                    help="data scaling level of the solver (and of the oracle baseline); default: "
+                         "1 for convolutions (block balancing inflates their spectral norm and "
+                         "the CG systems), 2 for the dense lasso blocks")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel choices instead of timing the candidates")
     ap.add_argument("--max-iters", type=int, default=None,
@@ -444,6 +446,8 @@ def main():
     cfg = w.workload(args.workload)
     log("workload", cfg["name"])
     fam = cfg["family"]
+    if args.normalize is None:
+        args.normalize = 2 if fam in ("lasso", "lasso_batch") else 1
     if fam == "deconv":
         out = run_deconv(args, cfg)
     elif fam == "lasso":

@@ -298,16 +298,24 @@ __global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha, in
     if (threadIdx.x == 0) part[0] = s0;
 }
 
+// u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta from k_tau_dots' partials
+// (slot 0), recomputed by every workgroup; the first Y tile's workgroup keeps
+// it for the projection.  Tiles of a second-order cone then store the cone's
+// head value (u_bar - v at its first row) and partial sums of squares of the
+// tail (Y partial slot 1).
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
     __shared__ double sh[VEC_NT / 64];
     const VecTile tl = tb.yt[blockIdx.x];
-    if (tl.seg < 0) return;
     const InstDesc d = tb.inst[tl.inst];
-    gptr<const double> sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
+    const double x0 = inst_xsum(tb, d, 0, sh);
+    const double y0 = inst_ysum(tb, d, 0, sh);
+    const double ut = (sc[SC_TAU] + sc[SC_KAPPA] + x0 + y0) / sc[SC_ETA];
+    if ((int)blockIdx.x == d.yt0 && threadIdx.x == 0) sc[SC_UT] = ut;
+    if (tl.seg < 0) return;
     const SocSeg sg = tb.seg[tl.seg];
-    const double ut = sc[SC_UT];
     double s0 = 0.0;
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) {
         double ub;
@@ -316,16 +324,26 @@ __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
         else s0 = fma(pv, pv, s0);
     }
     s0 = block_sum<VEC_NT>(s0, sh);
-    if (threadIdx.x == 0) tb.ypart[4 * (int64_t)blockIdx.x] = s0;
+    if (threadIdx.x == 0) tb.ypart[4 * (int64_t)blockIdx.x + 1] = s0;
 }
 
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
+    __shared__ double sh[VEC_NT / 64];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
-    gptr<const double> sc = scal(d);
+    gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
     const double ut = sc[SC_UT];
+    if (!xt.is_y && xt.index == d.xt0 && threadIdx.x == 0) {
+        // tau, kappa of the step (no workgroup of this kernel reads them)
+        const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
+        const double ubar = alpha * ut + (1.0 - alpha) * tau;
+        const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
+        sc[SC_KAPPA] = kap - ubar + tnew;
+        sc[SC_TAU] = tnew;
+        sc[SC_ITER] += 1.0;
+    }
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     if (!xt.is_y) {
         gptr<T> ux = xvec<T>(d, XU);
@@ -354,7 +372,7 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
     }
     const SocSeg sg = tb.seg[xt.t.seg];
     const double t = tb.seg_val[2 * xt.t.seg];
-    const double nz = sqrt(tb.seg_val[2 * xt.t.seg + 1]);
+    const double nz = sqrt(sum_parts_all<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 1, sh));
     // Pi(t, z): (t, z) if ||z|| <= t; 0 if ||z|| <= -t; ((t+||z||)/2)(1, z/||z||) otherwise
     int mode;
     double a = 0.0;
@@ -436,7 +454,6 @@ __global__ __launch_bounds__(VEC_NT) void k_resid(Tables tb, double eps, int max
 // tile order and finishes the scalar work of the method.
 enum FinMode : int {
     FIN_CG_INIT = 0,   // rr = ||r||^2, ||h||; CG tolerance and start flag
-    FIN_TAU,           // u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta; tau, kappa
     FIN_RESID,         // residuals, gap, certificates, status
     FIN_NORMS,         // ||b||, ||c||
     FIN_ETA            // eta = 1 + c^T g_x + b^T g_y; phase -> iterating
@@ -453,7 +470,7 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
     if (!gate_ok(sc, gate)) return;
     double x0 = 0, x1 = 0, x2 = 0, y0 = 0, y1 = 0, y2 = 0;
     const bool use_x = true;
-    const bool use_y = mode == FIN_TAU || mode == FIN_RESID || mode == FIN_NORMS || mode == FIN_ETA;
+    const bool use_y = mode == FIN_RESID || mode == FIN_NORMS || mode == FIN_ETA;
     const int nslot = (mode == FIN_RESID) ? 3 : (mode == FIN_CG_INIT ? 2 : 1);
     if (use_x) {
         x0 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
@@ -481,18 +498,6 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
             sc[SC_CGTOL] = tol;
             sc[SC_CGIT] = 0.0;
             sc[SC_CGACT] = (cg_max > 0 && sqrt(x0) > tol && std::isfinite(x0)) ? 1.0 : 0.0;
-            break;
-        }
-        case FIN_TAU: {
-            const double alpha = fa.a0;
-            const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
-            const double ut = (tau + kap + x0 + y0) / sc[SC_ETA];
-            const double ubar = alpha * ut + (1.0 - alpha) * tau;
-            const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
-            sc[SC_UT] = ut;
-            sc[SC_KAPPA] = kap - ubar + tnew;
-            sc[SC_TAU] = tnew;
-            sc[SC_ITER] += 1.0;
             break;
         }
         case FIN_RESID: {
@@ -527,15 +532,6 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
     }
 }
 
-// Tail sum of squares of every second-order cone (one workgroup per cone).
-__global__ __launch_bounds__(VEC_NT) void k_finalize_soc(Tables tb) {
-    __shared__ double sh[VEC_NT / 64];
-    const SocSeg sg = tb.seg[blockIdx.x];
-    const InstDesc d = tb.inst[sg.inst];
-    if (!gate_ok(scal(d), G_ADMM)) return;
-    const double ss = sum_parts<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 0, sh);
-    if (threadIdx.x == 0) tb.seg_val[2 * blockIdx.x + 1] = ss;
-}
 
 // ---------------------------------------------------------------- setup
 template <typename T>
@@ -802,13 +798,10 @@ void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
 }
 void launch_tau_dots(int prec, const Tables& t, double alpha, int form_zy, hipStream_t st) {
     CGS_DISPATCH(prec, k_tau_dots, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha, form_zy);
-    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_TAU, G_ADMM, FinArgs{alpha, 0, 0, 0, 0});
 }
 void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st) {
-    if (t.nseg > 0) {
-        CGS_DISPATCH(prec, k_soc_prep, t.ny_tiles, VEC_NT, st, t, alpha);
-        k_finalize_soc<<<t.nseg, VEC_NT, 0, st>>>(t);
-    }
+    // every Y tile: u~_tau for all instances, cone partials where there are cones
+    CGS_DISPATCH(prec, k_soc_prep, t.ny_tiles, VEC_NT, st, t, alpha);
 }
 void launch_project(int prec, const Tables& t, double alpha, hipStream_t st) {
     CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
