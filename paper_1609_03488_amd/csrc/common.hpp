@@ -155,7 +155,8 @@ struct DenseBlock {      // rows x cols block
     int64_t ld, ldt;     // leading dimensions of a (rows x ld) and at (cols x ldt)
     const void* a;       // working precision, row-major
     const void* at;      // its transpose, row-major
-    const void* a16;     // BF16 (round to nearest even) copies, CGS_BF16 only, or null
+    const void* a16;     // BF16 (round to nearest even) copies in the GEMM's packed
+                         // operand layout (rows padded to 32), CGS_BF16 only, or null
     const void* at16;
     const void* a16lo;   // BF16 rounding of the remainder a - a16 (refinement products)
     const void* at16lo;

@@ -86,7 +86,8 @@ size_t op_dev_bytes(const cgs_op& op, int precision) {
         if (b.kind == CGS_BLOCK_DENSE) {
             const size_t ld = dense_ld(b.cols), ldt = dense_ld(b.rows);
             tot += align256(b.rows * ld * sz) + align256(b.cols * ldt * sz);
-            if (precision == CGS_BF16) tot += 2 * (align256(b.rows * ld * 2) + align256(b.cols * ldt * 2));
+            if (precision == CGS_BF16)   // packed MFMA operands, rows padded to 32
+                tot += 2 * (align256(round_up(b.rows, 32) * ld * 2) + align256(round_up(b.cols, 32) * ldt * 2));
         }
     }
     return tot;
@@ -297,15 +298,15 @@ int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hi
             }
             if (precision == CGS_BF16) {
                 db.a16 = p;
-                p += align256(rows * ld * 2);
+                p += align256(round_up(rows, 32) * ld * 2);
                 db.a16lo = p;
-                p += align256(rows * ld * 2);
+                p += align256(round_up(rows, 32) * ld * 2);
                 db.at16 = p;
-                p += align256(cols * ldt * 2);
+                p += align256(round_up(cols, 32) * ldt * 2);
                 db.at16lo = p;
-                p += align256(cols * ldt * 2);
-                launch_to_bf16((const float*)db.a, (uint16_t*)db.a16, (uint16_t*)db.a16lo, rows * ld, st);
-                launch_to_bf16((const float*)db.at, (uint16_t*)db.at16, (uint16_t*)db.at16lo, cols * ldt, st);
+                p += align256(round_up(cols, 32) * ldt * 2);
+                launch_gemm_pack_w((const float*)db.a, rows, ld, (uint16_t*)db.a16, (uint16_t*)db.a16lo, st);
+                launch_gemm_pack_w((const float*)db.at, cols, ldt, (uint16_t*)db.at16, (uint16_t*)db.at16lo, st);
             }
         }
     }

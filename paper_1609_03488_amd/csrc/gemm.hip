@@ -18,6 +18,7 @@
 // k indices: k0 + 8 * (lane / 32) + e, e = 0..7.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -47,9 +48,21 @@ DEVI gptr<T> yvec_g(const InstDesc& d, int k) {
     return (gptr<T>)(d.base + REGION_HDR) + (int64_t)NXV * d.nxs + (int64_t)k * d.nys;
 }
 
+// ---------------------------------------------------------------- packed layouts
+// Operands are stored in the order a wave feeds them to the MFMA: for a tile of
+// 32 rows and a step of 16 k, lane l holds row (l % 32), k = 8 (l / 32) + e,
+// e = 0..7, as one 16-byte vector; the 64 lanes' vectors of a (tile, step)
+// are contiguous (1 KB), tiles are ksteps blocks apart.  Every operand load
+// of a wave is then one fully coalesced 1 KB read.
+DEVI int64_t packed_index(int64_t row, int64_t k, int64_t ksteps) {
+    const int64_t t = row >> 5, ks = k >> 4, kk = k & 15;
+    const int64_t lane = (row & 31) + 32 * (kk >> 3);
+    return ((t * ksteps + ks) * 64 + lane) * 8 + (kk & 7);
+}
+
 // ---------------------------------------------------------------- pack
-// panel[b][k] for b < mpad, k < kpad; instance b's input is its vector `in`
-// (X when !adj, Y when adj) starting at `off`, K valid entries.
+// Panels for b < mpad, k < kpad; instance b's input is its vector `in`
+// (X when !adj, Y when adj) starting at `off`, K valid entries; zeros beyond.
 __global__ __launch_bounds__(256) void k_gemm_pack(const InstDesc* insts, int ninst, int adj, int in,
                                                     int64_t off, int64_t K, int64_t kpad, int mpad,
                                                     uint16_t* hi, uint16_t* mid, uint16_t* lo) {
@@ -65,18 +78,39 @@ __global__ __launch_bounds__(256) void k_gemm_pack(const InstDesc* insts, int ni
     const uint16_t h = f32_to_bf16_rne(v);
     const float r1 = v - bf16_to_f32(h);           // exact in FP32
     const uint16_t md = f32_to_bf16_rne(r1);
-    hi[(int64_t)b * kpad + k] = h;
-    mid[(int64_t)b * kpad + k] = md;
-    lo[(int64_t)b * kpad + k] = f32_to_bf16_rne(r1 - bf16_to_f32(md));
+    const int64_t i = packed_index(b, k, kpad / 16);
+    hi[i] = h;
+    mid[i] = md;
+    lo[i] = f32_to_bf16_rne(r1 - bf16_to_f32(md));
     (void)mpad;
 }
 
+// W (rows x ld FP32, row-major, ld = kpad) -> packed BF16 hi and lo (BF16
+// rounding of the remainder), rows padded with zeros to a multiple of 32.
+__global__ __launch_bounds__(256) void k_gemm_pack_w(const float* w, int64_t rows, int64_t kpad,
+                                                      uint16_t* hi, uint16_t* lo) {
+    const int64_t rpad = (rows + 31) / 32 * 32;
+    const int64_t total = rpad * kpad;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / kpad, k = i - r * kpad;
+        const float v = r < rows ? w[r * kpad + k] : 0.0f;
+        const uint16_t h = f32_to_bf16_rne(v);
+        const int64_t j = packed_index(r, k, kpad / 16);
+        hi[j] = h;
+        lo[j] = f32_to_bf16_rne(v - bf16_to_f32(h));
+    }
+}
+
 // ---------------------------------------------------------------- gemm
-// grid: (N tiles of 128, K splits, M tiles of 64); 4 waves, wave w owns columns
-// [n0 + 32w, n0 + 32w + 32) and both 32-row halves of the 64-row M tile.
+// grid: (N tiles of 128, K splits, M tiles of 64); 4 waves, wave w owns the
+// 32-column tile 4 blockIdx.x + w and both 32-row halves of the 64-row M tile.
+// Four K steps are loaded (1 KB per operand and step, coalesced) before their
+// products are issued, so that 16-28 loads per lane are in flight.
 constexpr int GEMM_NT = 256;
 constexpr int GEMM_TN = 128;
 constexpr int GEMM_TM = 64;
+constexpr int GEMM_U = 4;
 
 __global__ __launch_bounds__(GEMM_NT) void k_gemm_bf16(const uint16_t* __restrict__ w_hi,
                                                        const uint16_t* __restrict__ w_lo,
@@ -88,60 +122,86 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_bf16(const uint16_t* __restric
                                                        float* __restrict__ part, int64_t npad,
                                                        int mpad) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t n0 = (int64_t)blockIdx.x * GEMM_TN + wave * 32;
+    const int64_t nt = (int64_t)blockIdx.x * (GEMM_TN / 32) + wave;
+    if (nt * 32 >= npad) return;
     const int s = blockIdx.y;
-    const int m0 = blockIdx.z * GEMM_TM;
-    const int64_t kstep0 = (int64_t)s * ksteps_per_split;
+    const int mt0 = blockIdx.z * (GEMM_TM / 32);
     const int64_t ksteps = kpad / 16;
+    const int64_t kstep0 = (int64_t)s * ksteps_per_split;
     int64_t kend = kstep0 + ksteps_per_split;
     if (kend > ksteps) kend = ksteps;
-    const int row = lane & 31, half = lane >> 5;
-    // lanes past the last row of W read a valid row; their columns (>= N) are
-    // never reduced
-    const int64_t wn = (n0 + row < N) ? (n0 + row) : (N - 1);
-    const u16x8* wh = reinterpret_cast<const u16x8*>(w_hi + wn * kpad) + half;
-    const u16x8* wl = reinterpret_cast<const u16x8*>(w_lo + wn * kpad) + half;
-    const u16x8* xh0 = reinterpret_cast<const u16x8*>(x_hi + (int64_t)(m0 + row) * kpad) + half;
-    const u16x8* xh1 = reinterpret_cast<const u16x8*>(x_hi + (int64_t)(m0 + 32 + row) * kpad) + half;
-    const u16x8* xm0 = reinterpret_cast<const u16x8*>(x_mid + (int64_t)(m0 + row) * kpad) + half;
-    const u16x8* xm1 = reinterpret_cast<const u16x8*>(x_mid + (int64_t)(m0 + 32 + row) * kpad) + half;
-    const u16x8* xl0 = reinterpret_cast<const u16x8*>(x_lo + (int64_t)(m0 + row) * kpad) + half;
-    const u16x8* xl1 = reinterpret_cast<const u16x8*>(x_lo + (int64_t)(m0 + 32 + row) * kpad) + half;
+    // tiles of W past the padded rows do not exist: clamp (their columns are
+    // never reduced)
+    const int64_t ntw = nt < (N + 31) / 32 ? nt : (N + 31) / 32 - 1;
+    const u16x8* wh = reinterpret_cast<const u16x8*>(w_hi) + ntw * ksteps * 64 + lane;
+    const u16x8* wl = reinterpret_cast<const u16x8*>(w_lo) + ntw * ksteps * 64 + lane;
+    const u16x8* xh0 = reinterpret_cast<const u16x8*>(x_hi) + (int64_t)mt0 * ksteps * 64 + lane;
+    const u16x8* xm0 = reinterpret_cast<const u16x8*>(x_mid) + (int64_t)mt0 * ksteps * 64 + lane;
+    const u16x8* xl0 = reinterpret_cast<const u16x8*>(x_lo) + (int64_t)mt0 * ksteps * 64 + lane;
+    const int64_t mstride = ksteps * 64;   // next 32-row M tile
     f32x16 acc0 = {}, acc1 = {};
-    for (int64_t ks = kstep0; ks < kend; ++ks) {
-        const int64_t o = ks * 2;   // 16 bf16 per step = two 8-element vectors
+    int64_t ks = kstep0;
+    for (; ks + GEMM_U <= kend; ks += GEMM_U) {
+        u16x8 w[GEMM_U], wlo[GEMM_U], h0[GEMM_U], h1[GEMM_U], m0[GEMM_U], m1[GEMM_U], l0[GEMM_U],
+            l1[GEMM_U];
+#pragma unroll
+        for (int u = 0; u < GEMM_U; ++u) {
+            const int64_t o = (ks + u) * 64;
+            w[u] = wh[o];
+            if (corr) wlo[u] = wl[o];
+            h0[u] = xh0[o];
+            h1[u] = xh0[o + mstride];
+            m0[u] = xm0[o];
+            m1[u] = xm0[o + mstride];
+            l0[u] = xl0[o];
+            l1[u] = xl0[o + mstride];
+        }
+#pragma unroll
+        for (int u = 0; u < GEMM_U; ++u) {
+            const bf16x8 bw = __builtin_bit_cast(bf16x8, w[u]);
+            // smallest terms first
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, l0[u]), bw, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, l1[u]), bw, acc1, 0, 0, 0);
+            if (corr) {
+                const bf16x8 bwl = __builtin_bit_cast(bf16x8, wlo[u]);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, m0[u]), bwl, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, m1[u]), bwl, acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, h0[u]), bwl, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, h1[u]), bwl, acc1, 0, 0, 0);
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, m0[u]), bw, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, m1[u]), bw, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, h0[u]), bw, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, h1[u]), bw, acc1, 0, 0, 0);
+        }
+    }
+    for (; ks < kend; ++ks) {
+        const int64_t o = ks * 64;
         const bf16x8 bw = __builtin_bit_cast(bf16x8, wh[o]);
-        const bf16x8 a0 = __builtin_bit_cast(bf16x8, xh0[o]);
-        const bf16x8 a1 = __builtin_bit_cast(bf16x8, xh1[o]);
-        const bf16x8 a0m = __builtin_bit_cast(bf16x8, xm0[o]);
-        const bf16x8 a1m = __builtin_bit_cast(bf16x8, xm1[o]);
-        const bf16x8 a0l = __builtin_bit_cast(bf16x8, xl0[o]);
-        const bf16x8 a1l = __builtin_bit_cast(bf16x8, xl1[o]);
-        // smallest terms first
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, bw, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, bw, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xl0[o]), bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xl0[o + mstride]), bw, acc1, 0, 0, 0);
         if (corr) {
             const bf16x8 bwl = __builtin_bit_cast(bf16x8, wl[o]);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0m, bwl, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1m, bwl, acc1, 0, 0, 0);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bwl, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bwl, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xm0[o]), bwl, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xm0[o + mstride]), bwl, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xh0[o]), bwl, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xh0[o + mstride]), bwl, acc1, 0, 0, 0);
         }
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0m, bw, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1m, bw, acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xm0[o]), bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xm0[o + mstride]), bw, acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xh0[o]), bw, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, xh0[o + mstride]), bw, acc1, 0, 0, 0);
     }
     // D layout of a 32x32 MFMA: column = lane % 32, row = 8 (v / 4) + 4 (lane / 32) + v % 4
-    const int64_t col = n0 + row;
+    const int row = lane & 31, half = lane >> 5;
+    const int64_t col = nt * 32 + row;
+    const int m0r = mt0 * 32;
     float* p = part + (int64_t)s * mpad * npad;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int r = 8 * (v / 4) + 4 * half + (v % 4);
-        if (col < npad) {
-            p[(int64_t)(m0 + r) * npad + col] = acc0[v];
-            p[(int64_t)(m0 + 32 + r) * npad + col] = acc1[v];
-        }
+        p[(int64_t)(m0r + r) * npad + col] = acc0[v];
+        p[(int64_t)(m0r + 32 + r) * npad + col] = acc1[v];
     }
 }
 
@@ -193,6 +253,13 @@ GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst, int target_wgs) {
 }
 
 size_t gemm_part_bytes(const GemmPlan& g) { return (size_t)g.nsplit * g.mpad * g.npad * sizeof(float); }
+
+void launch_gemm_pack_w(const float* w, int64_t rows, int64_t kpad, uint16_t* hi, uint16_t* lo,
+                        hipStream_t st) {
+    const int64_t total = (rows + 31) / 32 * 32 * kpad;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    if (blocks > 0) k_gemm_pack_w<<<(unsigned)blocks, 256, 0, st>>>(w, rows, kpad, hi, lo);
+}
 
 void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
                        double sigma, int gate, int corr, uint16_t* panel, size_t panel_stride,

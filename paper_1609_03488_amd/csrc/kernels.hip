@@ -728,22 +728,6 @@ __global__ void k_set_scalar(const InstDesc* insts, int inst, int slot, double v
     if (threadIdx.x == 0 && blockIdx.x == 0) reinterpret_cast<double*>(insts[inst].base)[slot] = v;
 }
 
-DEVI uint16_t bf16_rne(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40u);
-    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);   // round to nearest even
-}
-
-__global__ void k_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float x = src[i];
-        const uint16_t h = bf16_rne(x);
-        hi[i] = h;
-        lo[i] = bf16_rne(x - __uint_as_float((uint32_t)h << 16));
-    }
-}
-
 // ---------------------------------------------------------------- launchers
 #define CGS_DISPATCH(prec, KERNEL, grid, block, st, ...)                                 \
     do {                                                                                \
@@ -861,9 +845,6 @@ void launch_gather_scalars(const InstDesc* insts, int ninst, double* out, hipStr
 }
 void launch_set_scalar(const InstDesc* insts, int inst, int slot, double v, hipStream_t st) {
     k_set_scalar<<<1, 64, 0, st>>>(insts, inst, slot, v);
-}
-void launch_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st) {
-    if (n > 0) k_to_bf16<<<flat_grid(n, 256), 256, 0, st>>>(src, hi, lo, n);
 }
 
 }  // namespace cgs

@@ -102,7 +102,6 @@ void launch_gather_scalars(const InstDesc* insts, int ninst, double* out, hipStr
 void launch_set_scalar(const InstDesc* insts, int inst, int slot, double v, hipStream_t st);
 // BF16 copies (round to nearest even) of a working-precision FP32 matrix: hi =
 // bf16(x), lo = bf16(x - hi)
-void launch_to_bf16(const float* src, uint16_t* hi, uint16_t* lo, int64_t n, hipStream_t st);
 
 // ---- fused small-instance steps (fused.hip): one workgroup per instance runs
 // nsteps ADMM steps and, with check, the termination test and the exact
@@ -127,6 +126,9 @@ struct GemmPlan {
     int nsplit;             // K splits (partials reduced in fixed order)
     int64_t npad;
 };
+// W (rows x kpad FP32, row-major) -> BF16 hi / lo in the GEMM's packed operand layout
+void launch_gemm_pack_w(const float* w, int64_t rows, int64_t kpad, uint16_t* hi, uint16_t* lo,
+                        hipStream_t st);
 // target_wgs: workgroups to aim for (K splits = target / (N tiles x M tiles), >= 1, <= 64)
 GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst, int target_wgs);
 constexpr int GEMM_TARGET_MAX = 1024;   // largest target the autotuner tries (sizes the partials)
