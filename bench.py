@@ -430,7 +430,7 @@ def main():
                     help="MiB copied by a plain device copy after the run (counter calibration)")
     ap.add_argument("--serve-count", type=int, default=None)
     ap.add_argument("--serve-ws", type=int, default=16, help="server workspace, GiB")
-    ap.add_argument("--serve-cg", type=int, default=10, help="CG iterations per step, upper bound")
+    ap.add_argument("--serve-cg", type=int, default=3, help="CG iterations per step, upper bound")
     ap.add_argument("--serve-fused-max", type=int, default=16384,
                     help="largest n + m served by the fused one-workgroup-per-request path "
                          "(larger requests take one launch per kernel)")

@@ -285,6 +285,10 @@ int cgs_server_submit(cgs_server* sv, const cgs_op* op, int64_t l, const int64_t
 int cgs_server_step(cgs_server* sv, int32_t steps, int64_t* n_running);
 /* Status of a ticket (CGS_RUNNING while unfinished). */
 int cgs_server_poll(cgs_server* sv, int64_t ticket, int32_t* status);
+/* Tickets of the finished problems not yet fetched or cancelled, in admission
+ * order: up to `cap` of them into tickets (may be NULL when cap = 0); *count
+ * receives how many there are in all. */
+int cgs_server_finished(const cgs_server* sv, int64_t* tickets, int64_t cap, int64_t* count);
 /* Copy out a finished problem's x (n), y (m), s (m) and info, and release its
  * slot and memory. */
 int cgs_server_fetch(cgs_server* sv, int64_t ticket, double* x, double* y, double* sl,

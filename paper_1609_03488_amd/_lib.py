@@ -104,6 +104,7 @@ _SIGS = {
     "cgs_server_submit": (C.c_int, [_P, _P, _I64, _I64P, _I64, _DP, _DP, _I64P]),
     "cgs_server_step": (C.c_int, [_P, C.c_int32, _I64P]),
     "cgs_server_poll": (C.c_int, [_P, _I64, C.POINTER(C.c_int32)]),
+    "cgs_server_finished": (C.c_int, [_P, _I64P, C.c_int64, _I64P]),
     "cgs_server_fetch": (C.c_int, [_P, _I64, _DP, _DP, _DP, C.POINTER(Info)]),
     "cgs_server_cancel": (C.c_int, [_P, _I64]),
     "cgs_server_usage": (C.c_int, [_P, _I64P, C.POINTER(C.c_size_t)]),
@@ -366,6 +367,16 @@ class Server:
         s = C.c_int32()
         _check(lib().cgs_server_poll(self._h, int(ticket), C.byref(s)))
         return int(s.value)
+
+    def finished(self) -> List[int]:
+        """Tickets that have finished and await fetch (admission order)."""
+        n = C.c_int64()
+        _check(lib().cgs_server_finished(self._h, None, 0, C.byref(n)))
+        if n.value == 0:
+            return []
+        buf = (C.c_int64 * n.value)()
+        _check(lib().cgs_server_finished(self._h, buf, n.value, C.byref(n)))
+        return list(buf)
 
     def fetch(self, ticket: int):
         n, m = self._shapes.pop(int(ticket))

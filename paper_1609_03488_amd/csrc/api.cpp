@@ -922,6 +922,19 @@ int cgs_server_poll(cgs_server* sv, int64_t ticket, int32_t* status) {
     return CGS_OK;
 }
 
+int cgs_server_finished(const cgs_server* sv, int64_t* tickets, int64_t cap, int64_t* count) {
+    if (!sv || !count) return fail(CGS_EINVAL, "null argument");
+    if (cap < 0 || (cap > 0 && !tickets)) return fail(CGS_EINVAL, "bad ticket buffer");
+    int64_t k = 0;
+    for (const auto& r : sv->live)
+        if (r->finished) {
+            if (k < cap) tickets[k] = r->ticket;
+            ++k;
+        }
+    *count = k;
+    return CGS_OK;
+}
+
 int cgs_server_fetch(cgs_server* sv, int64_t ticket, double* x, double* y, double* sl, cgs_info* info) {
     if (!sv) return fail(CGS_EINVAL, "server is null");
     const int i = find_req(sv, ticket);

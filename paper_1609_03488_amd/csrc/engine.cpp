@@ -446,6 +446,9 @@ size_t image_work_bytes(const TableImage& im) {
 // ---------------------------------------------------------------- engine
 Engine::~Engine() {
     drop_graph();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     if (tab_host) (void)hipHostFree(tab_host);
     if (scal_host) (void)hipHostFree(scal_host);
     if (stg.host) (void)hipHostFree(stg.host);
@@ -675,7 +678,28 @@ void Engine::fused_steps(int nsteps, int check) {
 }
 
 int Engine::round(int nsteps) {
-    if (n_fused) fused_steps(nsteps, 1);
+    bool forked = false;
+    if (n_fused && n_multi && stream != nullptr) {
+        // both paths in the round: the fused launch runs on the side stream
+        // beside the other instances' kernels (they touch disjoint instance
+        // regions and partial buffers) and the main stream waits for it
+        if (!side) {
+            CGS_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+            CGS_HIP(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+            CGS_HIP(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        }
+        CGS_HIP(hipEventRecord(ev_fork, stream));
+        CGS_HIP(hipStreamWaitEvent(side, ev_fork, 0));
+        hipStream_t main_stream = stream;
+        stream = side;
+        fused_steps(nsteps, 1);
+        stream = main_stream;
+        CGS_HIP(hipGetLastError());
+        CGS_HIP(hipEventRecord(ev_join, side));
+        forked = true;
+    } else if (n_fused) {
+        fused_steps(nsteps, 1);
+    }
     if (!n_multi) {
         CGS_HIP(hipGetLastError());
         return CGS_OK;
@@ -700,6 +724,7 @@ int Engine::round(int nsteps) {
         for (int i = 0; i < nsteps; ++i) admm_step();
         check();
     }
+    if (forked) CGS_HIP(hipStreamWaitEvent(stream, ev_join, 0));
     CGS_HIP(hipGetLastError());
     return CGS_OK;
 }

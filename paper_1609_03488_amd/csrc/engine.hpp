@@ -171,6 +171,11 @@ class Engine {
     float* gemm_part = nullptr;
     int gemm_target = 512;       // GEMM workgroups aimed for (autotuned)
 
+    // side stream for the fused launch, overlapped with the one-launch-per-kernel
+    // round of the other instances (disjoint memory); default priority
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_steps = -1;

@@ -15,7 +15,7 @@ from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 
-from ._lib import RUNNING, Server, Settings, FP32
+from ._lib import Server, Settings, FP32
 from .problems import ConeProblem
 
 
@@ -80,8 +80,8 @@ def replay(requests: Sequence, make_problem: Callable[[object], ConeProblem], *,
             continue
         server.step(steps_per_call)
         tdone = now()
-        for ticket in list(running):
-            if server.poll(ticket) != RUNNING:
+        for ticket in server.finished():
+            if ticket in running:
                 req, pr, tadm = running.pop(ticket)
                 x, _, _, info = server.fetch(ticket)
                 done.append(Completed(req.rid, req.arrival_s, tadm, tdone, info["status"],

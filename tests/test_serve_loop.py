@@ -55,6 +55,9 @@ class FakeServer:
     def poll(self, t):
         return 0 if self.live[t][1] > 0 else 1
 
+    def finished(self):
+        return [t for t, v in self.live.items() if v[1] <= 0]
+
     def fetch(self, t):
         req, _ = self.live.pop(t)
         self.free += req.size
