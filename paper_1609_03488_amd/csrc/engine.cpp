@@ -492,6 +492,7 @@ int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_double
 
 int Engine::build(const std::vector<InstRec>& r) {
     recs = r;
+    rounds_since_build = 0;
     build_image(recs, precision, im);
     // each instance's path depends on its own size only (never on the mix)
     n_fused = n_multi = 0;
@@ -704,7 +705,12 @@ int Engine::round(int nsteps) {
         CGS_HIP(hipGetLastError());
         return CGS_OK;
     }
-    const bool use_g = st.use_graph && stream != nullptr && nsteps == st.check_every;
+    // Capture and instantiation cost more than launching one round directly,
+    // so a graph is captured only for tables that have already served a round
+    // (a server rebuilds them whenever requests arrive or leave).
+    const bool use_g = st.use_graph && stream != nullptr && nsteps == st.check_every &&
+                       (graph_exec || rounds_since_build >= 1);
+    ++rounds_since_build;
     if (use_g) {
         if (!graph_exec || graph_steps != nsteps || graph_cg != cg_launch) {
             drop_graph();

@@ -180,6 +180,7 @@ class Engine {
     hipGraphExec_t graph_exec = nullptr;
     int graph_steps = -1;
     int graph_cg = -1;
+    int rounds_since_build = 0;   // a graph is captured only once the tables have held a round
 
     ~Engine();
     int init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles);
