@@ -69,8 +69,8 @@ enum Scal : int {
     SC_CGMAX,                                  // most CG iterations of a step since the last check
     SC_CGMAXLAST,                              // ... over the previous check interval
     SC_SB, SC_SC,                              // data scales: b^ = sb D b, c^ = sc E c
-    SC_RR2,                                    // CG ||r||^2, second slot: iteration i reads
-                                               // slot i % 2 (SC_RR, SC_RR2), writes the other
+    SC_CGRUN,                                  // CG iteration whose products are in place
+                                               // (set by the dot kernel, -1 at CG start)
     NSC_USED
 };
 constexpr int NSC = 32;      // doubles reserved per instance (256 bytes)

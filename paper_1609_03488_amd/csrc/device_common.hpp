@@ -64,6 +64,29 @@ DEVI double block_sum(double v, double* sh) {
     return r;
 }
 
+// Four sums over the workgroup in a fixed order, returned to every thread
+// (sh: 4 * NT / 64 doubles).
+template <int NT>
+DEVI void block_sum4(double (&s)[4], double* sh) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = wave_sum(s[j]);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sh[j * (NT / 64) + w] = s[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) r += sh[j * (NT / 64) + i];
+        s[j] = r;
+    }
+    __syncthreads();
+}
+
 // Fixed-order sum of partial slot j over tiles [t0, t1) (partials of the
 // previous kernel: the kernel boundary makes them visible).
 template <int NT>
@@ -96,6 +119,17 @@ DEVI double inst_xsum(const Tables& tb, const InstDesc& d, int j, double* sh) {
     const double r = sh[0];
     __syncthreads();
     return r;
+}
+
+// All four X-tile partial slots of the instance at once (sh: 4 * VEC_NT / 64).
+DEVI void inst_xsum4(const Tables& tb, const InstDesc& d, double (&s)[4], double* sh) {
+    s[0] = s[1] = s[2] = s[3] = 0.0;
+    for (int i = d.xt0 + (int)threadIdx.x; i < d.xt1; i += VEC_NT) {
+        const double* pp = tb.xpart + 4 * (int64_t)i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[j] += pp[j];
+    }
+    block_sum4<VEC_NT>(s, sh);
 }
 
 // The same for the instance's Y-tile partials.

@@ -616,9 +616,8 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
 void Engine::cg_iter(int z, int gate, int cg_max, int track, int it) {
     apply(0, YT, XP, -1, 1.0, gate);
     apply(1, XQ, YT, XP, 1.0, gate);
-    launch_cg_dot(prec, T, XP, XQ, gate, stream);
-    launch_cg_update(prec, T, z, XR, XP, XQ, it, gate, track, stream);
-    launch_cg_dir(prec, T, XR, XP, it, cg_max, gate, stream);
+    launch_cg_dot(prec, T, XP, XQ, XR, it, gate, stream);
+    launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream);
 }
 
 // One ADMM step of the homogeneous self-dual embedding.  The CG warm start z

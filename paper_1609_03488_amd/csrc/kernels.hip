@@ -162,98 +162,99 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_init(Tables tb, int z, int r, int
     }
 }
 
+// Partials of <p, q>, ||r||^2, <r, q> and ||q||^2 (slots 0..3).  The first
+// tile's workgroup records the iteration whose products are now in place: the
+// update of that iteration runs only if it finds this mark, so the update can
+// clear the run flag without racing its own workgroups' gate tests.
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int gate) {
-    __shared__ double sh[VEC_NT / 64];
+__global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int r, int it, int gate) {
+    __shared__ double sh[4 * (VEC_NT / 64)];
     const VecTile tl = tb.xt[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate)) return;
+    if ((int)blockIdx.x == d.xt0 && threadIdx.x == 0) sc[SC_CGRUN] = (double)it;
     gptr<const T> pv = xvec<T>(d, p);
     gptr<const T> qv = xvec<T>(d, q);
-    double s0 = 0.0;
-    for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
-        s0 = fma((double)pv[i], (double)qv[i], s0);
-    s0 = block_sum<VEC_NT>(s0, sh);
-    if (threadIdx.x == 0) tb.xpart[4 * (int64_t)blockIdx.x] = s0;   // slot 0
+    gptr<const T> rv = xvec<T>(d, r);
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) {
+        const double pi = (double)pv[i], qi = (double)qv[i], ri = (double)rv[i];
+        s[0] = fma(pi, qi, s[0]);
+        s[1] = fma(ri, ri, s[1]);
+        s[2] = fma(ri, qi, s[2]);
+        s[3] = fma(qi, qi, s[3]);
+    }
+    block_sum4<VEC_NT>(s, sh);
+    if (threadIdx.x == 0) {
+        double* part = tb.xpart + 4 * (int64_t)blockIdx.x;
+        part[0] = s[0];
+        part[1] = s[1];
+        part[2] = s[2];
+        part[3] = s[3];
+    }
 }
 
-// z += alpha p, r -= alpha q (and the carried K z, A z when tracking), with
-// alpha = ||r||^2 / <p, q> recomputed by every workgroup from k_cg_dot's
-// partials; ||r'||^2 partials go to slot 1.  CG iteration `slot` = it % 2.
+// One CG step after the products: alpha = ||r||^2 / <p, q>; z += alpha p;
+// r' = r - alpha q (and the carried K z, A z when tracking); then the next
+// direction p = r' + beta p in the same pass.  beta needs ||r'||^2 before r'
+// exists anywhere but in this kernel, so it is taken from the expansion
+// ||r - alpha q||^2 = ||r||^2 - 2 alpha <r, q> + alpha^2 ||q||^2 of the FP64
+// partials of k_cg_dot (the same quantity the method defines, evaluated
+// without a second reduction pass); the stop test uses the same value.  Every
+// workgroup sums the partials in the same fixed order.  The first tile's
+// workgroup records alpha, beta, the counters and the run flag.
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q, int slot,
-                                                      int gate, int track) {
-    __shared__ double sh[VEC_NT / 64];
+__global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q, int it,
+                                                      int cg_max, int gate, int track) {
+    __shared__ double sh[4 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
-    if (!gate_ok(sc, gate)) return;
-    const double pq = inst_xsum(tb, d, 0, sh);
-    const double al = sc[slot ? SC_RR2 : SC_RR] / pq;
+    if (!gate_ok(sc, gate) || sc[SC_CGRUN] != (double)it) return;
+    double s[4];
+    inst_xsum4(tb, d, s, sh);
+    const double pq = s[0], rr = s[1], rq = s[2], qq = s[3];
+    const double al = rr / pq;
     const bool ok = pq > 0.0 && std::isfinite(al);
+    const double rr1 = fma(al * al, qq, fma(-2.0 * al, rq, rr));
+    const double be = rr > 0.0 ? rr1 / rr : 0.0;
+    const bool more = ok && std::isfinite(rr1) && sqrt(rr1) > sc[SC_CGTOL] && it + 1 < cg_max;
     if (!xt.is_y && xt.index == d.xt0 && threadIdx.x == 0) {
         sc[SC_PQ] = pq;
         sc[SC_ALPHA] = ok ? al : 0.0;
-        if (!ok) sc[SC_CGACT] = 0.0;   // every workgroup reaches the same decision
+        sc[SC_RR] = ok ? rr1 : rr;
+        sc[SC_BETA] = be;
+        if (ok) {
+            sc[SC_CGIT] += 1.0;
+            sc[SC_CGTOT] += 1.0;
+            if (sc[SC_CGIT] > sc[SC_CGMAX]) sc[SC_CGMAX] = sc[SC_CGIT];
+            if (gate == G_SETUP) sc[SC_SETUPIT] += 1.0;
+        }
+        sc[SC_CGACT] = more ? 1.0 : 0.0;
     }
     if (!ok) return;
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
-    double s0 = 0.0;
     if (!xt.is_y) {
         gptr<T> zv = xvec<T>(d, z);
         gptr<T> rv = xvec<T>(d, r);
-        gptr<const T> pv = xvec<T>(d, p);
+        gptr<T> pv = xvec<T>(d, p);
         gptr<const T> qv = xvec<T>(d, q);
         gptr<T> kz = xvec<T>(d, XK);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            const double qi = (double)qv[i];
-            zv[i] = (T)fma(al, (double)pv[i], (double)zv[i]);
+            const double qi = (double)qv[i], pi = (double)pv[i];
+            zv[i] = (T)fma(al, pi, (double)zv[i]);
             const T ri = (T)fma(-al, qi, (double)rv[i]);
             rv[i] = ri;
             if (track) kz[i] = (T)fma(al, qi, (double)kz[i]);
-            s0 = fma((double)ri, (double)ri, s0);
+            if (more) pv[i] = (T)fma(be, pi, (double)ri);
         }
-        s0 = block_sum<VEC_NT>(s0, sh);
-        if (threadIdx.x == 0) tb.xpart[4 * (int64_t)xt.index + 1] = s0;
     } else {
         gptr<T> az = yvec<T>(d, YA);
         gptr<const T> ap = yvec<T>(d, YT);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT)
             az[i] = (T)fma(al, (double)ap[i], (double)az[i]);
     }
-}
-
-// beta = ||r'||^2 / ||r||^2 and the stop test, recomputed by every workgroup
-// from k_cg_update's partials; p = r + beta p while CG goes on.  The first
-// tile's workgroup records the new ||r||^2 (in the other slot, which no
-// workgroup of this kernel reads), the counters and the run flag.
-template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_cg_dir(Tables tb, int r, int p, int slot, int it,
-                                                   int cg_max, int gate) {
-    __shared__ double sh[VEC_NT / 64];
-    const VecTile tl = tb.xt[blockIdx.x];
-    const InstDesc d = tb.inst[tl.inst];
-    gptr<double> sc = scal(d);
-    if (!gate_ok(sc, gate)) return;
-    const double rr = inst_xsum(tb, d, 1, sh);
-    const double prev = sc[slot ? SC_RR2 : SC_RR];
-    const double be = prev > 0.0 ? rr / prev : 0.0;
-    const bool more = std::isfinite(rr) && sqrt(rr) > sc[SC_CGTOL] && it + 1 < cg_max;
-    if ((int)blockIdx.x == d.xt0 && threadIdx.x == 0) {
-        sc[slot ? SC_RR : SC_RR2] = rr;
-        sc[SC_BETA] = be;
-        sc[SC_CGIT] += 1.0;
-        sc[SC_CGTOT] += 1.0;
-        if (sc[SC_CGIT] > sc[SC_CGMAX]) sc[SC_CGMAX] = sc[SC_CGIT];
-        if (gate == G_SETUP_CG) sc[SC_SETUPIT] += 1.0;
-        sc[SC_CGACT] = more ? 1.0 : 0.0;
-    }
-    if (!more) return;
-    gptr<const T> rv = xvec<T>(d, r);
-    gptr<T> pv = xvec<T>(d, p);
-    for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT)
-        pv[i] = (T)fma(be, (double)pv[i], (double)rv[i]);
 }
 
 template <typename T>
@@ -497,6 +498,7 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
             sc[SC_HN] = hn;
             sc[SC_CGTOL] = tol;
             sc[SC_CGIT] = 0.0;
+            sc[SC_CGRUN] = -1.0;
             sc[SC_CGACT] = (cg_max > 0 && sqrt(x0) > tol && std::isfinite(x0)) ? 1.0 : 0.0;
             break;
         }
@@ -766,16 +768,15 @@ void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h
                  floor_, cg_max, gate);
     k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_INIT, gate, FinArgs{zeta, rate, floor_, cg_max, 0});
 }
-void launch_cg_dot(int prec, const Tables& t, int p, int q, int gate, hipStream_t st) {
-    CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, gate);
+void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int gate, hipStream_t st) {
+    CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, r, it, gate);
 }
-void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int gate,
-                      int track, hipStream_t st) {
+void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
+                      int gate, int track, hipStream_t st) {
+    // the update's own gate is the phase test of the CG gate plus the mark of k_cg_dot
+    const int g = gate == G_ADMM_CG ? G_ADMM : gate == G_SETUP_CG ? G_SETUP : G_ALL;
     CGS_DISPATCH(prec, k_cg_update, t.nx_tiles + (track ? t.ny_tiles : 0), VEC_NT, st, t, z, r, p, q,
-                 it & 1, gate, track);
-}
-void launch_cg_dir(int prec, const Tables& t, int r, int p, int it, int cg_max, int gate, hipStream_t st) {
-    CGS_DISPATCH(prec, k_cg_dir, t.nx_tiles, VEC_NT, st, t, r, p, it & 1, it, cg_max, gate);
+                 it, cg_max, g, track);
 }
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_wy, t.ny_tiles, VEC_NT, st, t, gate);

@@ -50,15 +50,15 @@ void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int o
 //       tol = ||h|| * max(floor, zeta / (k+1)^rate), CG active iff ||r|| > tol.
 void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h, int have_q,
                     double zeta, double rate, double floor, int cg_max, int gate, hipStream_t st);
-// partials of <p, q>
-void launch_cg_dot(int prec, const Tables& t, int p, int q, int gate, hipStream_t st);
-// alpha = rr / <p, q>; z += alpha p; r -= alpha q; partials of ||r||^2
+// partials of <p, q>, ||r||^2, <r, q>, ||q||^2; marks iteration `it` as in progress
+void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int gate, hipStream_t st);
+// alpha = ||r||^2 / <p, q>; z += alpha p; r -= alpha q; beta = ||r'||^2 / ||r||^2
+// (from the dot partials); stop test (||r'|| <= tol or it + 1 = cg_max);
+// p = r' + beta p while CG goes on.
 // track = 1: also K z += alpha q and A z += alpha (A p) (carried products)
-// `it`: CG iteration of the current loop (0-based; selects the rr slot)
-void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int gate,
-                      int track, hipStream_t st);
-// rr' , beta, stop test (it + 1 < cg_max); p = r + beta p
-void launch_cg_dir(int prec, const Tables& t, int r, int p, int it, int cg_max, int gate, hipStream_t st);
+// `it`: CG iteration of the current loop (must match the preceding launch_cg_dot)
+void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
+                      int gate, int track, hipStream_t st);
 
 // ---- ADMM step pieces (Section V-B: subspace projection, then cone projection)
 // w_y = u_y + v_s
