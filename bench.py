@@ -13,7 +13,10 @@ Other workloads (`--workload`): `deconv_n1000_k101` (FP64, 1e-6),
 `lasso_5000x10000` (FP32 dense lasso), `lasso_batch64_2000x8000` (64 lasso
 instances sharing A, BF16 MFMA GEMMs; a step solves all 64), and
 `serve_deconv_2000req` (replay of the 2000-request Poisson trace through the
-continuous-batching server; one step = the whole replay).
+continuous-batching server; one step = the whole replay),
+`regls_dense_6000x3000` / `regls_conv_3000_k1365` (Section V-A: regularized least
+squares by matrix-free CG to the 1e-8 relative residual, FP64; one step = one
+solve) and `lasso_conv_3000_k1365` (lasso with the convolution operator).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -29,6 +32,7 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-1e-4 KKT residual & CG matvecs/s; batched solves/s, p50/p99 latency"
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published dense FP32 vector peak
+PEAK_FP64_VECTOR_TFLOPS = 78.6    # MI355X published FP64 vector peak
 PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
 
@@ -247,6 +251,151 @@ def run_lasso(args, cfg):
     return out
 
 
+# ---------------------------------------------------------------- regularized least squares (CG)
+def run_regls(args, cfg):
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1609_03488_amd as P
+
+    d = w.make_regls(cfg)
+    n = cfg["n"]
+    stream = torch.cuda.Stream()
+    prec = P.FP64 if cfg["precision"] == "fp64" else P.FP32
+    if d["kind"] == "dense":
+        rs = P.RegLS(d["lam"], A=d["A"], precision=prec, stream=stream)
+    else:
+        rs = P.RegLS(d["lam"], taps=d["c"], n=n, precision=prec, stream=stream)
+    for i in range(args.warmup):
+        x, it = rs.solve(d["b"], tol=cfg["tol"])
+        log(f"{cfg['name']} warmup {i}: {it} CG iterations")
+    torch.cuda.synchronize()
+    its = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, it = rs.solve(d["b"], tol=cfg["tol"])
+        its.append(it)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"{cfg['name']}: {its} CG iterations, {1e3 * elapsed / args.steps:.2f} ms per solve")
+    m = rs.m
+    if d["kind"] == "dense":
+        t_a, t_at = rs.solver.kernel_time(2, 20), rs.solver.kernel_time(3, 20)
+        bytes_a = 8.0 * m * n
+        achieved = 2 * bytes_a / ((t_a + t_at) * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "kernel": f"k_gemv<double> (A and A^T, FP64, {bytes_a / 1e6:.0f} MB each)",
+                "bytes_per_launch": bytes_a, "launch_us": {"A": t_a * 1e3, "AT": t_at * 1e3}}
+    else:
+        k = cfg["k"]
+        t_a, t_at = rs.solver.kernel_time(0, 20), rs.solver.kernel_time(1, 20)
+        flop_a, flop_at = 2.0 * k * (n + k - 1), 2.0 * k * n
+        achieved = (flop_a + flop_at) / ((t_a + t_at) * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                "kernel": "k_conv<double> (FP64 vector-ALU convolution A and A^T)",
+                "flop_per_launch": {"A": flop_a, "AT": flop_at},
+                "launch_us": {"A": t_a * 1e3, "AT": t_at * 1e3}}
+    log(f"operator A {t_a * 1e3:.1f} us, A^T {t_at * 1e3:.1f} us, {roof['achieved']:.1f} {roof['unit']}")
+    import oracle
+    verify = None
+    if not args.no_verify:
+        rhs = oracle.regls_rhs(d)
+        ref = oracle.regls_solution(d)
+        verify = {"rel_residual_fp64": float(np.linalg.norm(oracle.regls_apply_normal(d, x) - rhs) / np.linalg.norm(rhs)),
+                  "rel_err_vs_closed_form": float(np.linalg.norm(x - ref) / np.linalg.norm(ref)),
+                  "objective": oracle.regls_objective(d, x)}
+        log("verify", verify)
+    cpu = None
+    if not args.no_cpu_baseline:
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            oracle.regls_solution(d)
+            reps += 1
+            if time.perf_counter() - t0 > 5.0 or reps >= 50:
+                break
+        t = (time.perf_counter() - t0) / reps
+        cpu = {"value": 1.0 / t, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": (f"the oracle's closed form (FP64 {'dense' if d['kind'] == 'dense' else 'banded'} "
+                          f"Cholesky of lam I + A^T A and its solve), {reps} repetitions, {t:.3f} s each")}
+        log("cpu", cpu)
+    cfgout = {"workload": cfg["name"], "n": n, "m": m, "lam": float(d["lam"]), "tol": cfg["tol"],
+              "operator": d["kind"]}
+    if d["kind"] == "conv":
+        cfgout["kernel_taps"] = cfg["k"]
+    out = base_record(args, args.steps / elapsed, "solves/s", elapsed,
+                      "f64" if prec == P.FP64 else "f32", cfgout)
+    out.update({"time_to_tol_s": elapsed / args.steps, "cg_iters": its[-1],
+                "cg_matvecs_per_s": sum(its) / elapsed, "roofline": roof, "cpu_baseline": cpu,
+                "verify": verify})
+    rs.close()
+    return out
+
+
+# ---------------------------------------------------------------- lasso with a convolution operator
+def run_lasso_conv(args, cfg):
+    import numpy as np
+    import torch
+    import workloads as w
+    import paper_1609_03488_amd as P
+
+    d = w.make_conv_lasso(cfg)
+    n, k = cfg["n"], cfg["k"]
+    pr = P.conv_lasso_problem(d["c"], d["b"], d["lam"])
+    stream = torch.cuda.Stream()
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10, normalize=args.normalize)
+    if args.max_iters:
+        st.max_iters = args.max_iters
+    s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
+    s.set_data(0, pr.b, pr.c)
+    mfma = 0
+    if not args.no_autotune:
+        mfma = s.autotune(reps=10)["conv_mfma"]
+        log(f"autotune: convolution on {'matrix cores' if mfma else 'vector ALU'}")
+    infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
+    last = infos[-1][0]
+    t_a, t_at = s.kernel_time(0, 20), s.kernel_time(1, 20)
+    flop_a, flop_at = 2.0 * k * (n + k - 1), 2.0 * k * n
+    achieved = (flop_a + flop_at) / ((t_a + t_at) * 1e-3) / 1e12
+    log(f"conv A {t_a * 1e3:.1f} us, A^T {t_at * 1e3:.1f} us, {achieved:.1f} TFLOP/s")
+    import oracle
+    prog = oracle.conv_lasso_program(d["c"], d["b"], d["lam"])
+    verify = None
+    if not args.no_verify:
+        x, y, sl = s.solution(0)
+        rp, rd, gap, _, _ = oracle.scs.residuals(prog, x, y, 1.0, sl)
+        xs = x[:n]
+        r = np.convolve(d["c"], xs) - d["b"]
+        f = float(0.5 * (r @ r) + d["lam"] * np.sum(np.abs(xs)))
+        verify = {"res_pri_fp64": rp, "res_dual_fp64": rd, "gap_fp64": gap, "objective": f}
+        log("verify", verify)
+    cpu = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        res = oracle.scs_solve(prog, eps=cfg["eps"], check_every=10, normalize=args.normalize)
+        t = time.perf_counter() - t0
+        cpu = {"value": 1.0 / t, "unit": "solves/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": f"complete FP64 oracle solve (banded Cholesky of 3I+4C^T C, {res.iters} ADMM "
+                         f"iterations, status {res.status}) in {t:.1f} s"}
+        log("cpu", cpu)
+    out = base_record(args, args.steps / elapsed, "solves/s", elapsed, "f32",
+                      {"workload": cfg["name"], "n": n, "kernel_taps": k, "eps": cfg["eps"],
+                       "variables": 2 * n + 1, "constraints": 2 * n + (n + k - 1) + 2,
+                       "normalize": args.normalize, "scalars": "f64"})
+    out.update({
+        "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
+        "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed, "status": last["status_name"],
+        "roofline": {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": ("k_conv_mfma" if mfma else "k_conv<float>") + " (convolution A and A^T)",
+                     "flop_per_launch": {"A": flop_a, "AT": flop_at},
+                     "launch_us": {"A": t_a * 1e3, "AT": t_at * 1e3}},
+        "cpu_baseline": cpu, "verify": verify,
+    })
+    return out
+
+
 # ---------------------------------------------------------------- batched lasso (BF16 MFMA)
 def run_lasso_batch(args, cfg):
     import numpy as np
@@ -456,6 +605,10 @@ def main():
         out = run_lasso_batch(args, cfg)
     elif fam == "serve":
         out = run_serve(args, cfg)
+    elif fam == "regls":
+        out = run_regls(args, cfg)
+    elif fam == "lasso_conv":
+        out = run_lasso_conv(args, cfg)
     else:
         raise SystemExit(f"unknown workload family {fam}")
     if args.copy_calibration:

@@ -110,9 +110,11 @@ typedef struct {
                               all of them, CG loop inside the kernel); larger ones
                               take one launch per kernel spread over the chip.  The
                               path depends on an instance's own size only; 0
-                              disables (default 16384: one workgroup beats the
-                              launch overheads of a lone small instance, and a
-                              crowd of them fills the chip)                        */
+                              disables (default 16384: a crowd of such instances
+                              fills the chip one workgroup each).  Instances whose
+                              dense blocks hold more than 65536 entries always take
+                              the launch-per-kernel path (a dense product on one
+                              workgroup is 20-80x slower than spread over the chip) */
     int32_t conv_mfma;     /* 1: FP32 convolutions run on the matrix cores (16x16x4 FP32
                               MFMA over Toeplitz blocks of the taps); 0: vector ALU  */
     int32_t normalize;     /* data scaling the iteration runs on: 1 (default):
@@ -125,7 +127,12 @@ typedef struct {
                               as given.  Termination and returned points are those
                               of the original problem; the raw state and the
                               diagnostic apply / normal solve use the scaled data. */
-    int32_t reserved[3];
+    int32_t fused_lone_max; /* a solver holding a single instance (batch 1) takes the
+                              fused path only for n + m <= min(fused_max,
+                              fused_lone_max): alone, one workgroup races the whole
+                              chip, and measured per-step times cross near n + m =
+                              8000 (default 8192; 0: fused_max alone decides)       */
+    int32_t reserved[2];
 } cgs_settings;
 
 /* Per-instance result. */
@@ -234,7 +241,7 @@ int cgs_solver_set_state(cgs_solver* s, int64_t inst, const double* ux, const do
  * (info: batch entries; status stays CGS_RUNNING unless a test passes). */
 int cgs_solver_residuals(cgs_solver* s, cgs_info* info);
 /* One operator application on the device in the working precision, for
- * instance 0's operator as the iteration sees it (D A E when normalize = 1):
+ * instance 0's operator as the iteration sees it (D A E when normalize = 2):
  * out = A in (transpose = 0, in: n, out: m) or out = A^T in (transpose = 1,
  * in: m, out: n).  Host FP64 arrays. */
 int cgs_solver_apply(cgs_solver* s, int32_t transpose, const double* in, double* out);

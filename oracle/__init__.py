@@ -18,6 +18,8 @@ What it computes (plain, slow, obviously correct, float64 throughout):
 * ``scs``      -- the homogeneous self-dual embedding ADMM iteration the paper
   runs ("SCS", Sections II-D and V-B), with the linear-subspace step solved
   exactly through the factorisation instead of by conjugate gradients.
+* ``regls``    -- the closed-form solution of regularized least squares
+  (Section V-A), computed by a direct factorisation.
 * ``polish``   -- a textbook active-set step that turns the iterative result into
   an exact optimum with a KKT certificate (nonnegative least squares / lasso).
 
@@ -25,14 +27,16 @@ Every function cites the passage of the paper it follows; where the paper is
 silent the reading taken is stated in the function's docstring.
 """
 from .cones import proj_nonneg, proj_soc, proj_cone, in_cone
-from .program import ConeProgram, deconv_program, lasso_program, dense_program
+from .program import ConeProgram, deconv_program, lasso_program, dense_program, conv_lasso_program
 from .equil import Scaling, equilibrate, scaled_program
 from .scs import scs_solve, ScsResult, hsde_subspace_step, prepare
 from .polish import polish_deconv, polish_lasso, deconv_objective, lasso_objective
+from .regls import regls_solution, regls_rhs, regls_apply_normal, regls_objective
 
 __all__ = [
     "proj_nonneg", "proj_soc", "proj_cone", "in_cone",
-    "ConeProgram", "deconv_program", "lasso_program", "dense_program",
+    "ConeProgram", "deconv_program", "lasso_program", "dense_program", "conv_lasso_program",
+    "regls_solution", "regls_rhs", "regls_apply_normal", "regls_objective",
     "Scaling", "equilibrate", "scaled_program",
     "scs_solve", "ScsResult", "hsde_subspace_step", "prepare",
     "polish_deconv", "polish_lasso", "deconv_objective", "lasso_objective",

@@ -127,6 +127,22 @@ def autocorrelation(c: np.ndarray) -> np.ndarray:
     return np.array([np.dot(c[:k - d], c[d:]) for d in range(k)])
 
 
+def gram_toeplitz_solver(c: np.ndarray, n: int, diag: float, w: float) -> Callable:
+    """Solver for ``(diag I + w C^T C) v = r`` with ``C`` the full convolution by
+    ``c`` on ``n`` inputs.  ``C^T C`` is the symmetric Toeplitz matrix of the
+    kernel autocorrelation (no boundary terms: the convolution is full), so the
+    matrix is factored by a banded Cholesky of half-bandwidth ``k - 1``."""
+    k = c.shape[0]
+    ac = autocorrelation(c)
+    kd = min(k - 1, n - 1)
+    ab = np.zeros((kd + 1, n))          # upper banded storage
+    for d in range(kd + 1):
+        ab[kd - d, d:] = w * ac[d]
+    ab[kd, :] += diag
+    cb = sla.cholesky_banded(ab, lower=False, check_finite=False)
+    return lambda r: sla.cho_solve_banded((cb, False), r, check_finite=False)
+
+
 def deconv_program(c: np.ndarray, b_obs: np.ndarray) -> ConeProgram:
     """Nonnegative deconvolution (Section V-C, eq. 6) as a cone program.
 
@@ -175,18 +191,12 @@ def deconv_program(c: np.ndarray, b_obs: np.ndarray) -> ConeProgram:
     def banded(p, q, r):
         # I + A^T A for A = [[-p I, 0], [0, -q], [-r C, 0]]:
         # blockdiag((1 + p^2) I + r^2 C^T C, 1 + q^2)
-        ac = autocorrelation(c)
-        kd = min(k - 1, n - 1)
-        ab = np.zeros((kd + 1, n))          # upper banded storage
-        for d in range(kd + 1):
-            ab[kd - d, d:] = r * r * ac[d]
-        ab[kd, :] += 1.0 + p * p
-        cb = sla.cholesky_banded(ab, lower=False, check_finite=False)
+        gram = gram_toeplitz_solver(c, n, 1.0 + p * p, r * r)
         tt = 1.0 + q * q
 
         def solve(rhs):
             out = np.empty(nv)
-            out[:n] = sla.cho_solve_banded((cb, False), rhs[:n], check_finite=False)
+            out[:n] = gram(rhs[:n])
             out[n] = rhs[n] / tt
             return out
         return Factor(solve, "banded")
@@ -287,6 +297,88 @@ def lasso_program(A: np.ndarray, b_obs: np.ndarray, lam: float) -> ConeProgram:
     return ConeProgram(nv, m, b, cc, 2 * n0, [m0 + 2], apply, apply_T, explicit,
                        lambda: blockdiag(2.0, 2.0, 2.0, 2.0), "lasso",
                        {"A": A, "b_obs": b_obs, "lam": float(lam), "n": n0, "m": m0},
+                       blocks=[(0, n0, 0, n0), (0, n0, n0, n0), (n0, n0, 0, n0), (n0, n0, n0, n0),
+                               (2 * n0, 1, 2 * n0, 1), (i_mid, m0, 0, n0), (m - 1, 1, 2 * n0, 1)],
+                       apply_sq=apply_sq, scaled_factor=scaled_factor)
+
+
+def conv_lasso_program(c: np.ndarray, b_obs: np.ndarray, lam: float) -> ConeProgram:
+    """Lasso with a convolution operator (Section V-B, the convolution column
+    of Table II): ``minimize (1/2)||c * x - b||^2 + lam ||x||_1`` in the cone form
+    of :func:`lasso_program` with the dense block replaced by the full
+    convolution ``C`` (``n + k - 1`` rows).  ``2n + 1`` variables,
+    ``2n + (n + k - 1) + 2`` constraints and ``4n + kn + 2`` nonzeros;
+    ``I + A_c^T A_c = blockdiag(3I + 4 C^T C, 3I, 3)`` with ``C^T C`` banded
+    Toeplitz (banded Cholesky).
+    """
+    c = np.asarray(c, dtype=np.float64)
+    b_obs = np.asarray(b_obs, dtype=np.float64)
+    k = c.shape[0]
+    n0 = b_obs.shape[0] - k + 1
+    if n0 < 1:
+        raise ValueError("observation shorter than kernel")
+    m0 = n0 + k - 1
+    nv = 2 * n0 + 1
+    m = 2 * n0 + m0 + 2
+    b = np.concatenate([np.zeros(2 * n0), [1.0], -2.0 * b_obs, [-1.0]])
+    cc = np.concatenate([np.zeros(n0), np.full(n0, float(lam)), [0.5]])
+    i_mid = 2 * n0 + 1
+
+    def apply(z):
+        x, t, u = z[:n0], z[n0:2 * n0], z[2 * n0]
+        return np.concatenate([x - t, -x - t, [-u], -2.0 * np.convolve(c, x), [-u]])
+
+    def apply_T(y):
+        y1, y2 = y[:n0], y[n0:2 * n0]
+        out = np.empty(nv)
+        out[:n0] = y1 - y2 - 2.0 * np.correlate(y[i_mid:i_mid + m0], c, mode="valid")
+        out[n0:2 * n0] = -y1 - y2
+        out[2 * n0] = -y[2 * n0] - y[m - 1]
+        return out
+
+    def explicit():
+        Ac = np.zeros((m, nv))
+        I = np.eye(n0)
+        Ac[:n0, :n0] = I
+        Ac[:n0, n0:2 * n0] = -I
+        Ac[n0:2 * n0, :n0] = -I
+        Ac[n0:2 * n0, n0:2 * n0] = -I
+        Ac[2 * n0, 2 * n0] = -1.0
+        Ac[i_mid:i_mid + m0, :n0] = -2.0 * conv_matrix(c, n0)
+        Ac[m - 1, 2 * n0] = -1.0
+        return Ac
+
+    def blockdiag(dx, dt, du, r):
+        # as in lasso_program, with the Gram block r^2 C^T C banded Toeplitz
+        gram = gram_toeplitz_solver(c, n0, 1.0 + dx, r * r)
+
+        def solve(rhs):
+            out = np.empty(nv)
+            out[:n0] = gram(rhs[:n0])
+            out[n0:2 * n0] = rhs[n0:2 * n0] / (1.0 + dt)
+            out[2 * n0] = rhs[2 * n0] / (1.0 + du)
+            return out
+        return Factor(solve, "conv-lasso-banded")
+
+    def scaled_factor(D, E):
+        _require_constant(D, [(0, n0), (n0, 2 * n0), (2 * n0, m)])
+        _require_constant(E, [(0, n0), (n0, 2 * n0), (2 * n0, nv)])
+        d1, d2, d3 = D[0], D[n0], D[2 * n0]
+        ex, et, eu = E[0], E[n0], E[2 * n0]
+        if d1 != d2:
+            raise ValueError("rows t - x and t + x must carry the same scale")
+        return blockdiag(2.0 * (d1 * ex) ** 2, 2.0 * (d1 * et) ** 2, 2.0 * (d3 * eu) ** 2,
+                         2.0 * d3 * ex)
+
+    c2 = c * c
+
+    def apply_sq(z):
+        x, t, u = z[:n0], z[n0:2 * n0], z[2 * n0]
+        return np.concatenate([x + t, x + t, [u], 4.0 * np.convolve(c2, x), [u]])
+
+    return ConeProgram(nv, m, b, cc, 2 * n0, [m0 + 2], apply, apply_T, explicit,
+                       lambda: blockdiag(2.0, 2.0, 2.0, 2.0), "lasso_conv",
+                       {"c": c, "b_obs": b_obs, "lam": float(lam), "n": n0, "m": m0, "k": k},
                        blocks=[(0, n0, 0, n0), (0, n0, n0, n0), (n0, n0, 0, n0), (n0, n0, n0, n0),
                                (2 * n0, 1, 2 * n0, 1), (i_mid, m0, 0, n0), (m - 1, 1, 2 * n0, 1)],
                        apply_sq=apply_sq, scaled_factor=scaled_factor)

@@ -11,4 +11,5 @@ from ._lib import (  # noqa: F401
     FP64, FP32, BF16, SOLVED, MAX_ITERS, INFEASIBLE, UNBOUNDED, NUMERICAL, RUNNING,
     STATUS_NAMES,
 )
-from .problems import deconv_problem, lasso_problem, ConeProblem  # noqa: F401
+from .problems import deconv_problem, lasso_problem, conv_lasso_problem, ConeProblem  # noqa: F401
+from .regls import RegLS  # noqa: F401

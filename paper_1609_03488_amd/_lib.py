@@ -32,7 +32,7 @@ class Settings(C.Structure):
         ("setup_tol", C.c_double), ("setup_max_iters", C.c_int32), ("use_graph", C.c_int32),
         ("bf16_phase1_digits", C.c_int32), ("cg_adaptive", C.c_int32),
         ("fused_max", C.c_int32), ("conv_mfma", C.c_int32), ("normalize", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("fused_lone_max", C.c_int32), ("reserved", C.c_int32 * 2),
     ]
 
     @classmethod
@@ -295,7 +295,7 @@ class Solver:
 
     def apply(self, v, transpose: bool = False) -> np.ndarray:
         """A v (or A^T v) on the device, A as the iteration sees it (D A E when
-        normalize = 1)."""
+        normalize = 2)."""
         v = _f64(v, self.m if transpose else self.n)
         out = np.empty(self.n if transpose else self.m)
         _check(lib().cgs_solver_apply(self._h, 1 if transpose else 0, _dp(v), _dp(out)))

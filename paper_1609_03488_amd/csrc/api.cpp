@@ -251,6 +251,7 @@ void cgs_settings_default(cgs_settings* st) {
     st->bf16_phase1_digits = 3;
     st->cg_adaptive = 1;
     st->fused_max = 16384;
+    st->fused_lone_max = 8192;
     st->conv_mfma = 1;
     st->normalize = 1;
 }
@@ -309,6 +310,7 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
     e.st = *st;
     e.stream = (hipStream_t)stream;
     e.cg_launch = st->cg_max_iters;
+    e.lone = batch == 1 ? 1 : 0;
     char* p = (char*)workspace;
     e.tab_dev = p; e.tab_cap = L.tab; p += L.tab;
     e.work_dev = p; e.work_cap = L.work; p += L.work;

@@ -52,6 +52,7 @@ int validate_settings(const cgs_settings* s) {
     if (s->bf16_phase1_digits < 0 || s->bf16_phase1_digits > 15)
         return fail(CGS_EINVAL, "bf16_phase1_digits must be in [0, 15]");
     if (s->normalize < 0 || s->normalize > 2) return fail(CGS_EINVAL, "normalize must be 0, 1 or 2");
+    if (s->fused_max < 0 || s->fused_lone_max < 0) return fail(CGS_EINVAL, "fused_max, fused_lone_max must be >= 0");
     return CGS_OK;
 }
 
@@ -494,10 +495,15 @@ int Engine::build(const std::vector<InstRec>& r) {
     recs = r;
     rounds_since_build = 0;
     build_image(recs, precision, im);
-    // each instance's path depends on its own size only (never on the mix)
+    // each instance's path depends on its own size only (never on the mix);
+    // a solver's single instance has the whole chip to itself on the other path
     n_fused = n_multi = 0;
+    const int64_t lim = (lone && st.fused_lone_max > 0) ? std::min(st.fused_max, st.fused_lone_max)
+                                                        : (int64_t)st.fused_max;
     for (InstDesc& d : im.inst) {
-        d.fused = (st.fused_max > 0 && !use_gemm && d.n + d.m <= (int64_t)st.fused_max) ? 1 : 0;
+        int64_t dense = 0;
+        for (int b = d.db0; b < d.db1; ++b) dense += im.dblk[b].rows * im.dblk[b].cols;
+        d.fused = (st.fused_max > 0 && !use_gemm && d.n + d.m <= lim && dense <= FUSED_DENSE_MAX) ? 1 : 0;
         (d.fused ? n_fused : n_multi) += 1;
     }
     const size_t tb = image_table_bytes(im), wb = image_work_bytes(im);

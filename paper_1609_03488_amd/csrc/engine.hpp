@@ -135,6 +135,9 @@ struct TableImage {
 void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im);
 size_t image_table_bytes(const TableImage& im);
 size_t image_work_bytes(const TableImage& im);
+// dense entries above which an instance never takes the fused path (a dense
+// product on one workgroup is 20-80x slower than spread over the chip)
+constexpr int64_t FUSED_DENSE_MAX = 65536;
 
 // ---------------------------------------------------------------- engine
 class Engine {
@@ -162,6 +165,7 @@ class Engine {
     // fused path: one workgroup per instance runs whole steps (instances with
     // n + m <= fused_max); the others take one launch per kernel
     int n_fused = 0, n_multi = 0;
+    int lone = 0;                // a solver with a single instance (fused_lone_max applies)
     int fused_kc = 8;
     // batched BF16 MFMA path for dense blocks shared by every instance
     int use_gemm = 0;

@@ -14,6 +14,9 @@ matrix: convolution and dense data enter as blocks (Sections III-A, IV).
       rows [t - x >= 0 | t + x >= 0 | SOC(u + 1, 2(A x - b_obs), u - 1)]
       A = [[I, -I, 0], [-I, -I, 0], [0, 0, -1], [-2A, 0, 0], [0, 0, -1]]
       b = [0, 0, 1, -2 b_obs, -1],  c = [0, lam 1, 1/2]
+
+* Lasso with a convolution operator (Table II, convolution column): the same
+  layout with the dense block ``-2A`` replaced by the full convolution ``-2C``.
 """
 from __future__ import annotations
 
@@ -66,6 +69,29 @@ def lasso_problem(A, b_obs, lam: float) -> ConeProblem:
     op.add_identity(n0, n0, n0, -1.0)
     op.add_identity(2 * n0, 2 * n0, 1, -1.0)  # u + 1
     op.add_dense(2 * n0 + 1, 0, A, -2.0)      # 2(A x - b)
+    op.add_identity(m - 1, 2 * n0, 1, -1.0)   # u - 1
+    b = np.concatenate([np.zeros(2 * n0), [1.0], -2.0 * b_obs, [-1.0]])
+    c = np.concatenate([np.zeros(n0), np.full(n0, float(lam)), [0.5]])
+    return ConeProblem(op, 2 * n0, [m0 + 2], b, c, n0)
+
+
+def conv_lasso_problem(taps, b_obs, lam: float) -> ConeProblem:
+    taps = np.asarray(taps, dtype=np.float64)
+    b_obs = np.asarray(b_obs, dtype=np.float64)
+    k = taps.shape[0]
+    n0 = b_obs.shape[0] - k + 1
+    if n0 < 1:
+        raise ValueError("observation shorter than the kernel")
+    m0 = n0 + k - 1
+    nv = 2 * n0 + 1
+    m = 2 * n0 + m0 + 2
+    op = Operator(m, nv)
+    op.add_identity(0, 0, n0, 1.0)            # t - x >= 0
+    op.add_identity(0, n0, n0, -1.0)
+    op.add_identity(n0, 0, n0, -1.0)          # t + x >= 0
+    op.add_identity(n0, n0, n0, -1.0)
+    op.add_identity(2 * n0, 2 * n0, 1, -1.0)  # u + 1
+    op.add_conv(2 * n0 + 1, 0, taps, n0, -2.0)   # 2(c * x - b)
     op.add_identity(m - 1, 2 * n0, 1, -1.0)   # u - 1
     b = np.concatenate([np.zeros(2 * n0), [1.0], -2.0 * b_obs, [-1.0]])
     c = np.concatenate([np.zeros(n0), np.full(n0, float(lam)), [0.5]])

@@ -132,6 +132,9 @@ def _equil_cases():
     yield P.deconv_problem(d["c"], d["b"]), o.deconv_program(d["c"], d["b"])
     d = w.lasso_instance(40, 70, 0.1, 1e-4, 4)
     yield P.lasso_problem(d["A"], d["b"], d["lam"]), o.lasso_program(d["A"], d["b"], d["lam"])
+    d = w.conv_lasso_instance(90, 17, 3.0, 1e-4, 6)
+    yield (P.conv_lasso_problem(d["c"], d["b"], d["lam"]),
+           o.conv_lasso_program(d["c"], d["b"], d["lam"]))
     # two dense blocks in different row ranges, a row no block touches, cones
     rng = np.random.default_rng(5)
     A1, A2 = rng.standard_normal((6, 3)), 10.0 * rng.standard_normal((5, 2))

@@ -121,3 +121,60 @@ def test_lasso_batch64_bf16_against_exact():
         assert max(rp, rd, gap) <= 1e-4, (i, rp, rd, gap)
         f = o.lasso_objective(d["A"], d["b"][i], d["lam"][i], x[:cfg["n"]])
         assert abs(f - ref["objective"]) / ref["objective"] <= 1e-4, (i, f, ref["objective"])
+
+
+@pytest.mark.parametrize("name", ["regls_dense_6000x3000", "regls_conv_3000_k1365"])
+def test_regls_paper_sizes_against_closed_form(name):
+    """Table I sizes (Section V-A): CG in FP64 to the paper's stop test
+    ||(lam I + A^T A) x - A^T b|| <= 1e-8 ||A^T b||, recomputed here in FP64;
+    the iterate is within cond * 1e-8 of the closed form."""
+    cfg = w.workload(name)
+    _say(name)
+    d = w.make_regls(cfg)
+    if d["kind"] == "dense":
+        rs = P.RegLS(d["lam"], A=d["A"], precision=P.FP64)
+    else:
+        rs = P.RegLS(d["lam"], taps=d["c"], n=cfg["n"], precision=P.FP64)
+    x, it = rs.solve(d["b"], tol=cfg["tol"])
+    rhs = o.regls_rhs(d)
+    res = np.linalg.norm(o.regls_apply_normal(d, x) - rhs) / np.linalg.norm(rhs)
+    assert res <= 1.01 * cfg["tol"], res
+    ref = o.regls_solution(d)
+    lam = float(d["lam"])
+    if d["kind"] == "dense":
+        sv = np.linalg.svd(d["A"], compute_uv=False)
+        cond = (lam + sv[0] ** 2) / (lam + sv[-1] ** 2)
+    else:
+        cond = (lam + 1.0) / lam
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    assert err <= 2 * cond * res + 1e-13, (err, cond, res)
+    assert 0 < it < 1000
+    rs.close()
+
+
+def test_lasso_conv_3000_fp32_against_exact():
+    """Lasso with the Table I convolution (Table II, convolution column) at the
+    workload's settings (FP32, eps = 1e-4, data scaling): solved, FP64 residuals
+    of the returned point within eps, and its objective no farther from the
+    KKT-certified optimum than twice the oracle's own eps = 1e-4 point (both
+    stored by tests/golden/make_reference.py) plus 1e-4 relative."""
+    cfg = w.workload("lasso_conv_3000_k1365")
+    _say(cfg["name"])
+    d = w.make_conv_lasso(cfg)
+    pr = P.conv_lasso_problem(d["c"], d["b"], d["lam"])
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10, normalize=1)
+    s = P.Solver(pr.op, pr.l, pr.q, st)
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, y, sl = s.solution(0)
+    prog = o.conv_lasso_program(d["c"], d["b"], d["lam"])
+    rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+    assert max(rp, rd, gap) <= 1.05 * cfg["eps"], (rp, rd, gap)
+    refs = REF[cfg["name"]]
+    opt, fr = refs["objective"], refs["scs_1e-4"]["objective"]
+    xs = x[:cfg["n"]]
+    r = np.convolve(d["c"], xs) - d["b"]
+    f = float(0.5 * (r @ r) + d["lam"] * np.sum(np.abs(xs)))
+    assert f >= opt * (1 - 1e-9)
+    assert f - opt <= 2 * (fr - opt) + 1e-4 * opt, (f, fr, opt)

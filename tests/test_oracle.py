@@ -87,6 +87,74 @@ def test_lasso_dimensions_and_nnz_match_table2():
     assert int(np.count_nonzero(Ac)) == row["nonzeros"]
 
 
+def test_conv_lasso_dimensions_and_nnz_match_table2():
+    """The nonzero count of the conv-lasso cone form is 4 n0 + k n0 + 2 (checked
+    on an explicit small instance), which at n0 = 3000, k = 1365 is the 4,107,002
+    of Table II; Table I's convolution has k n0 = 4,095,000 nonzeros."""
+    tab = json.load(open(os.path.join(GOLDEN, "paper_tables.json")))
+    for n0, k in ((40, 9), (25, 25)):
+        prog = o.conv_lasso_program(w.gaussian_kernel(k, k / 4), np.ones(n0 + k - 1), 0.1)
+        assert int(np.count_nonzero(prog.explicit())) == 4 * n0 + k * n0 + 2
+        assert int(np.count_nonzero(conv_matrix(w.gaussian_kernel(k, k / 4), n0))) == k * n0
+        assert prog.n == 2 * n0 + 1 and prog.m == 2 * n0 + (n0 + k - 1) + 2
+    row = tab["lasso_table2_conv"]
+    n0, k = row["n0"], row["k"]
+    assert 2 * n0 + 1 == row["variables"]
+    assert 4 * n0 + k * n0 + 2 == row["nonzeros"]
+    t1 = tab["regls_table1"]
+    assert t1["conv_k"] * t1["n"] == t1["conv_nonzeros"]
+    assert t1["dense_rows"] * t1["n"] == t1["dense_nonzeros"]
+
+
+def test_conv_lasso_canonical_form_kkt_with_polished_optimum():
+    """The conv-lasso cone program solved by the oracle and polished: the
+    polished point satisfies the lasso's subgradient optimality conditions (the
+    definition of the optimum) and the analytic primal-dual pair of the cone
+    form at it has zero residuals."""
+    d = w.conv_lasso_instance(70, 11, 2.0, 1e-4, 9)
+    prog = o.conv_lasso_program(d["c"], d["b"], d["lam"])
+    res = o.scs_solve(prog, eps=1e-8, max_iters=200_000)
+    assert res.status == "solved"
+    C = conv_matrix(d["c"], 70)
+    pol = o.polish_lasso(C, d["b"], d["lam"], res.x[:70])
+    assert pol["kkt_ok"]
+    g = C.T @ (d["b"] - C @ pol["x"])
+    S = pol["x"] != 0
+    assert np.all(np.abs(g[S] - d["lam"] * np.sign(pol["x"][S])) <= 1e-9 * d["lam"])
+    assert np.all(np.abs(g[~S]) <= d["lam"] * (1 + 1e-9))
+    z, y, s = _lasso_kkt_point(C, d["b"], d["lam"], pol["x"])
+    rp, rd, gap, pobj, _ = residuals(prog, z, y, 1.0, s)
+    assert rp < 1e-12 and rd < 1e-10 and gap < 1e-12
+    assert abs(pobj - pol["obj"]) < 1e-10
+
+
+@pytest.mark.parametrize("kind", ["dense", "conv"])
+def test_regls_closed_form_against_stacked_least_squares(kind):
+    """x* = (lam I + A^T A)^{-1} A^T b (eq. (5)) equals the least-squares solution
+    of the stacked system [A; sqrt(lam) I] x = [b; 0] computed by an orthogonal
+    factorisation (a different route to the same minimiser), and zeroes the
+    gradient A^T (A x - b) + lam x."""
+    if kind == "dense":
+        d = w.regls_instance("dense", 30, 3, m=50, lam=0.05)
+        A = d["A"]
+    else:
+        d = w.regls_instance("conv", 80, 4, k=21, sigma=5.0, lam=0.05)
+        A = conv_matrix(d["c"], 80)
+    lam = float(d["lam"])
+    x = o.regls_solution(d)
+    n = A.shape[1]
+    M = np.vstack([A, np.sqrt(lam) * np.eye(n)])
+    ref = np.linalg.lstsq(M, np.concatenate([d["b"], np.zeros(n)]), rcond=None)[0]
+    np.testing.assert_allclose(x, ref, rtol=1e-10, atol=1e-12)
+    grad = A.T @ (A @ x - d["b"]) + lam * x
+    assert np.linalg.norm(grad) <= 1e-11 * np.linalg.norm(A.T @ d["b"])
+    # the objective is minimal along random directions (convex quadratic)
+    rng = np.random.default_rng(0)
+    f0 = o.regls_objective(d, x)
+    for _ in range(5):
+        assert o.regls_objective(d, x + 1e-3 * rng.standard_normal(n)) > f0
+
+
 def test_convolution_primitive_matches_bruteforce_sum():
     rng = np.random.default_rng(0)
     c, x = rng.standard_normal(7), rng.standard_normal(19)
@@ -101,11 +169,13 @@ def test_convolution_primitive_matches_bruteforce_sum():
     np.testing.assert_allclose(conv_matrix(c, 19) @ x, y, atol=1e-13)
 
 
-@pytest.mark.parametrize("family", ["deconv", "lasso"])
+@pytest.mark.parametrize("family", ["deconv", "lasso", "lasso_conv"])
 def test_apply_adjoint_and_factor_against_explicit(family):
     rng = np.random.default_rng(1)
     if family == "deconv":
         prog = o.deconv_program(w.gaussian_kernel(9, 2.0), rng.standard_normal(40 + 8))
+    elif family == "lasso_conv":
+        prog = o.conv_lasso_program(w.gaussian_kernel(9, 2.0), rng.standard_normal(40 + 8), 0.3)
     else:
         prog = o.lasso_program(rng.standard_normal((15, 11)), rng.standard_normal(15), 0.3)
     A = prog.explicit()
@@ -357,6 +427,8 @@ def _small_programs():
     yield o.lasso_program(d["A"], d["b"], d["lam"])
     G = rng.standard_normal((9, 4))
     yield o.dense_program(G, rng.random(9), rng.standard_normal(4), 4, [5])
+    d = w.conv_lasso_instance(12, 5, 1.5, 1e-4, 7)
+    yield o.conv_lasso_program(d["c"], d["b"], d["lam"])
 
 
 def test_partition_merges_overlaps_and_keeps_gaps():
@@ -371,7 +443,7 @@ def test_groups_of_the_canonical_forms():
     nonnegative row blocks and the SOC; columns {x}, {t}, {u}.  One dense block:
     one group each way."""
     from oracle.equil import groups
-    dec, las, den = _small_programs()
+    dec, las, den, _ = _small_programs()
     rg, cg = groups(dec)
     assert np.bincount(rg).tolist() == [40, 40 + 9] and np.bincount(cg).tolist() == [40, 1]
     rg, cg = groups(las)
@@ -380,7 +452,7 @@ def test_groups_of_the_canonical_forms():
     assert np.bincount(rg).tolist() == [9] and np.bincount(cg).tolist() == [4]
 
 
-@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1, 2, 3])
 def test_group_norms_and_squared_apply_against_explicit(which):
     from oracle.equil import groups, group_norms
     prog = list(_small_programs())[which]
@@ -392,7 +464,7 @@ def test_group_norms_and_squared_apply_against_explicit(which):
             assert np.isclose(F[g, h], (A[np.ix_(rg == g, cg == h)] ** 2).sum(), rtol=1e-13, atol=1e-15)
 
 
-@pytest.mark.parametrize("which", [0, 1, 2])
+@pytest.mark.parametrize("which", [0, 1, 2, 3])
 def test_equilibrated_operator_properties(which):
     """The scaled matrix D A E: the cone is preserved (D constant on each SOC),
     its group RMS row norms agree across row groups and its column norms across

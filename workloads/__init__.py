@@ -31,6 +31,8 @@ __all__ = [
     "lasso_matrix",
     "lasso_instance",
     "serving_trace",
+    "regls_instance",
+    "conv_lasso_instance",
     "WORKLOADS",
     "workload",
 ]
@@ -105,6 +107,52 @@ def lasso_instance(m: int, n: int, density: float, noise_var: float, seed: int,
     return {"A": A, "x_true": x_true, "b": b, "lam": np.float64(lam)}
 
 
+def regls_instance(kind: str, n: int, seed: int, m: int = 0, k: int = 0, sigma: float = 0.0,
+                   noise_var: float = 1e-4, lam: float = 1e-2) -> Dict[str, object]:
+    """Regularized least-squares data (Section V-A, eq. 4).
+
+    ``kind = "dense"``: ``A`` is ``m x n`` with i.i.d. ``N(0, 1)`` entries;
+    ``kind = "conv"``: ``A x = c * x`` (full convolution, ``n + k - 1`` rows)
+    with the unit-sum ``k``-tap Gaussian of standard deviation ``sigma``.
+    ``x_hat ~ N(0, 1)`` (all ``n`` entries) and ``b = A x_hat + v`` with
+    ``v ~ N(0, noise_var)``; ``lam`` is returned unchanged (the paper does not
+    state its value).
+    """
+    rng = _rng(seed)
+    out: Dict[str, object] = {"kind": kind, "lam": np.float64(lam)}
+    if kind == "dense":
+        A = rng.standard_normal((m, n))
+        x_hat = rng.standard_normal(n)
+        clean = A @ x_hat
+        out["A"] = A
+    elif kind == "conv":
+        c = gaussian_kernel(k, sigma)
+        x_hat = rng.standard_normal(n)
+        clean = np.convolve(c, x_hat)
+        out["c"] = c
+    else:
+        raise ValueError(kind)
+    out["x_hat"] = x_hat
+    out["b"] = clean + rng.normal(0.0, math.sqrt(noise_var), size=clean.shape[0])
+    return out
+
+
+def conv_lasso_instance(n: int, k: int, sigma: float, noise_var: float, seed: int,
+                        lam_factor: float = 0.1) -> Dict[str, np.ndarray]:
+    """Lasso with a convolution operator (Section V-B, the convolution column of
+    Table II): ``A x = c * x`` as in :func:`regls_instance` (``kind = "conv"``),
+    ``x_true ~ N(0, 1)``, ``b = A x_true + v`` and
+    ``lam = lam_factor * ||A^T b||_inf`` (``A^T`` = valid correlation with ``c``).
+    """
+    rng = _rng(seed)
+    c = gaussian_kernel(k, sigma)
+    x_true = rng.standard_normal(n)
+    clean = np.convolve(c, x_true)
+    b = clean + rng.normal(0.0, math.sqrt(noise_var), size=clean.shape[0])
+    lam = lam_factor * float(np.max(np.abs(np.correlate(b, c, mode="valid"))))
+    return {"c": c, "x_true": x_true, "b": b, "lam": np.float64(lam)}
+
+
 @dataclasses.dataclass
 class Request:
     """One solve request of the serving workload."""
@@ -158,6 +206,16 @@ WORKLOADS = {
     "lasso_batch64_2000x8000": dict(family="lasso_batch", m=2000, n=8000, batch=64,
                                     density=0.05, noise_var=1e-4, seed=1004, eps=1e-4,
                                     precision="bf16"),
+    # Regularized least squares by CG (Section V-A, Table I): dense 6000 x 3000
+    # and a 3000-variable convolution whose 1365 taps give Table I's 4,095,000
+    # nonzeros; stopped at ||(lam I + A^T A) x - A^T b|| <= 1e-8 ||A^T b||.
+    "regls_dense_6000x3000": dict(family="regls", kind="dense", m=6000, n=3000, lam=1e-2,
+                                  noise_var=1e-4, seed=1006, tol=1e-8, precision="fp64"),
+    "regls_conv_3000_k1365": dict(family="regls", kind="conv", n=3000, k=1365, sigma=300.0,
+                                  lam=1e-2, noise_var=1e-4, seed=1007, tol=1e-8, precision="fp64"),
+    # Lasso with that convolution operator (Table II, convolution column).
+    "lasso_conv_3000_k1365": dict(family="lasso_conv", n=3000, k=1365, sigma=300.0,
+                                  noise_var=1e-4, seed=1008, eps=1e-4, precision="fp32"),
     # Serving stream of deconvolution requests.
     "serve_deconv_2000req": dict(family="serve", count=2000, rate=200.0, seed=1005,
                                  density=0.05, noise_var=1e-4, eps=1e-4, precision="fp32"),
@@ -178,6 +236,15 @@ def make_deconv(cfg: dict) -> Dict[str, np.ndarray]:
 
 def make_lasso(cfg: dict) -> Dict[str, np.ndarray]:
     return lasso_instance(cfg["m"], cfg["n"], cfg["density"], cfg["noise_var"], cfg["seed"])
+
+
+def make_regls(cfg: dict) -> Dict[str, object]:
+    return regls_instance(cfg["kind"], cfg["n"], cfg["seed"], m=cfg.get("m", 0), k=cfg.get("k", 0),
+                          sigma=cfg.get("sigma", 0.0), noise_var=cfg["noise_var"], lam=cfg["lam"])
+
+
+def make_conv_lasso(cfg: dict) -> Dict[str, np.ndarray]:
+    return conv_lasso_instance(cfg["n"], cfg["k"], cfg["sigma"], cfg["noise_var"], cfg["seed"])
 
 
 def make_lasso_batch(cfg: dict) -> Dict[str, object]:
