@@ -115,8 +115,14 @@ typedef struct {
                               dense blocks hold more than 65536 entries always take
                               the launch-per-kernel path (a dense product on one
                               workgroup is 20-80x slower than spread over the chip) */
-    int32_t conv_mfma;     /* 1: FP32 convolutions run on the matrix cores (16x16x4 FP32
-                              MFMA over Toeplitz blocks of the taps); 0: vector ALU  */
+    int32_t conv_mfma;     /* FP32 convolution engine.  1 (default): matrix cores
+                              (16x16x4 FP32 MFMA over Toeplitz blocks of the taps);
+                              2: FFT overlap-save (2048-point transforms in LDS, two
+                              real windows per complex transform) for kernels of up
+                              to 1536 taps, the matrix cores for longer ones; 0:
+                              vector ALU.  The products agree to their rounding
+                              (elementwise for 0 and 1; normwise per 2048-point
+                              window for 2)                                         */
     int32_t normalize;     /* data scaling the iteration runs on: 1 (default):
                               sb b, sc c with sb, sc bringing b and c to the mean row /
                               column norm of A (A itself, and so the conditioning of
@@ -260,10 +266,11 @@ int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, 
 int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* avg_ms);
 /* Autotuner: times the candidate kernel configurations on the solver's own
  * operator and vectors (HIP events, `reps` launches each) and keeps the
- * fastest -- the convolution engine for FP32 (vector ALU or matrix cores) and
- * the split-K width of the batched BF16 GEMM.  choice[2] (nullable) receives
- * {conv_mfma (or -1), GEMM workgroup target (or -1)}.  Results do not change:
- * only how the same products are computed. */
+ * fastest -- the convolution engine for FP32 (vector ALU, matrix cores, or FFT
+ * when the kernels are short enough) and the split-K width of the batched BF16
+ * GEMM.  choice[2] (nullable) receives {conv_mfma (or -1), GEMM workgroup
+ * target (or -1)}.  Only how the same products are computed changes: results
+ * agree to the products' rounding. */
 int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice);
 void cgs_solver_destroy(cgs_solver* s);
 

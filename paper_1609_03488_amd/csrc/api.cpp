@@ -429,9 +429,12 @@ int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice) {
     int32_t out[2] = {-1, -1};
     double best = 0.0;
     if (!e.cf.empty() && e.prec == 1) {
-        // convolution engine: vector ALU or matrix cores, A and A^T together
-        double t[2];
-        for (int m = 0; m < 2; ++m) {
+        // convolution engine: vector ALU, matrix cores or FFT, A and A^T together
+        bool fft = false;
+        for (const auto& c : e.cf) fft = fft || c.fft;
+        double t[3] = {0.0, 0.0, 0.0};
+        int bestm = 0;
+        for (int m = 0; m < (fft ? 3 : 2); ++m) {
             e.st.conv_mfma = m;
             double a = 0.0, b = 0.0;
             // untimed first launches: the runtime loads a kernel's code on its
@@ -441,8 +444,9 @@ int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice) {
             CGS_TRY(cgs_solver_kernel_time(s, 0, reps, &a));
             CGS_TRY(cgs_solver_kernel_time(s, 1, reps, &b));
             t[m] = a + b;
+            if (t[m] < t[bestm]) bestm = m;
         }
-        e.st.conv_mfma = t[1] < t[0] ? 1 : 0;
+        e.st.conv_mfma = bestm;
         out[0] = e.st.conv_mfma;
     }
     if (e.use_gemm) {

@@ -135,6 +135,10 @@ struct ConvBlock {       // full convolution of n_in inputs with k taps
     int64_t row0, col0, n_in, k, kpad;
     const void* w_fwd;   // taps reversed (correlation order for A x), kpad entries
     const void* w_adj;   // taps in order (correlation order for A^T y), kpad entries
+    // conj(DFT) of w_fwd / w_adj zero-padded to FFT_L points (float2), for the
+    // FFT engine (FP32 working precision and k <= FFT_KMAX), else null
+    const void* s_fwd;
+    const void* s_adj;
     double scale;
     // bit 0 (A x) / bit 1 (A^T y): no other convolution or dense block writes
     // into this block's output range, so the convolution writes the final
@@ -195,5 +199,7 @@ constexpr int CONV_KC_MAX_F64 = 1024;
 constexpr int CONV_R_F32 = 8;        // taps are padded to a multiple of this
 constexpr int CONV_R_F64 = 4;
 constexpr int DENSE_ROWS = 4;        // rows per dense-GEMV tile
+constexpr int FFT_L = 2048;          // points per transform of the FFT convolution engine
+constexpr int FFT_KMAX = 1536;       // longest kernel it takes (>= 513 outputs per window)
 
 }  // namespace cgs

@@ -1,0 +1,236 @@
+// FP32 convolution tiles by FFT (overlap-save), for kernels of up to FFT_KMAX taps.
+//
+// The correlation form out[o] = sum_t w[t] in[o + off + t] of A x and A^T y
+// (taps w of length k, zero beyond) is, for a window u[p] = in[o0 + off + p]
+// of FFT_L = L inputs, the circular correlation of u with w at the positions
+// p < B = L - k + 1, where no product wraps around.  The circular correlation
+// is IDFT(DFT(u) . conj(DFT(w))); conj(DFT(w)) is computed once per block and
+// direction when the operator is uploaded.  w is real, so the correlation maps
+// real inputs to real outputs: two windows (outputs o0.. and o0 + B..) travel
+// as the real and imaginary parts of one complex transform, and the real and
+// imaginary parts of the result are their outputs.  The inverse transform is a
+// forward one on the conjugate.
+//
+// Transforms: L = 2048 points in LDS, 256 threads, Stockham self-sorting
+// stages of radix 8, 8, 8 and 4 (Govindaraju et al., "High performance
+// discrete Fourier transforms on graphics processors", SC 2008); each thread
+// keeps the 8 values of its butterflies in registers; the twiddles come from a
+// table of the 2048 roots of unity (sincospi) that each workgroup builds in LDS
+// first.  One workgroup per two output blocks (2B outputs).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "device_common.hpp"
+
+namespace cgs {
+
+namespace {
+
+constexpr int FT = 256;   // threads per transform
+static_assert(FFT_L == 2048 && FT * 8 == FFT_L, "transform shape");
+
+struct cf {
+    float x, y;
+};
+DEVI cf cmul(cf a, cf b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+DEVI cf cadd(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
+DEVI cf csub(cf a, cf b) { return {a.x - b.x, a.y - b.y}; }
+DEVI cf mul_mi(cf a) { return {a.y, -a.x}; }   // times -i
+
+// 4- and 8-point DFTs (e^{-2 pi i n k / R}) in place, natural order
+DEVI void dft4(cf* v) {
+    const cf a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const cf a2 = cadd(v[1], v[3]), a3 = mul_mi(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+}
+DEVI void dft8(cf* v) {
+    cf e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft4(e);
+    dft4(o);
+    const float h = 0.70710678118654752f;
+    const cf w1 = {h * (o[1].x + o[1].y), h * (o[1].y - o[1].x)};   // o1 e^{-i pi/4}
+    const cf w2 = mul_mi(o[2]);                                     // o2 e^{-i pi/2}
+    const cf w3 = {h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y)};  // o3 e^{-3i pi/4}
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], w1);
+    v[5] = csub(e[1], w1);
+    v[2] = cadd(e[2], w2);
+    v[6] = csub(e[2], w2);
+    v[3] = cadd(e[3], w3);
+    v[7] = csub(e[3], w3);
+}
+// tw[i] = e^{-2 pi i i / FFT_L}, filled by every workgroup (8 values per thread)
+DEVI void fill_twiddles(cf* tw) {
+#pragma unroll
+    for (int r = 0; r < FFT_L / FT; ++r) {
+        const int i = threadIdx.x + FT * r;
+        float s, c;
+        sincospif(-2.0f * (float)i / (float)FFT_L, &s, &c);
+        tw[i] = {c, s};
+    }
+}
+template <int R>
+DEVI void twiddle(cf* v, int k, int span, const cf* tw) {   // v[r] *= e^{-2 pi i r k / span}
+    const int step = k * (FFT_L / span);
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(r * step) & (FFT_L - 1)]);
+}
+
+// Forward DFT of the 2048 values x[t + 256 r] that thread t holds in v[r].
+// On return thread t holds X[j + 512 r] (r = 0..3) in v[0..3] for j = t and
+// in v[4..7] for j = t + 256.  lds: 2048 entries; tw: the twiddle table (filled
+// before a barrier the first stage passes); ends with a barrier.
+DEVI void fft2048(cf* v, cf* lds, const cf* tw) {
+    const int t = threadIdx.x;
+    dft8(v);   // stage Ns = 1: outputs to 8 t + r
+#pragma unroll
+    for (int r = 0; r < 8; ++r) lds[8 * t + r] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int Ns = 8; Ns <= 64; Ns *= 8) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = lds[t + FT * r];
+        const int k = t % Ns;
+        twiddle<8>(v, k, Ns * 8, tw);
+        dft8(v);
+        __syncthreads();
+        const int base = (t / Ns) * Ns * 8 + k;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) lds[base + r * Ns] = v[r];
+        __syncthreads();
+    }
+    // stage Ns = 512, radix 4: butterflies t and t + 256
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int j = t + FT * h;
+        cf* w = v + 4 * h;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = lds[j + 512 * r];
+        twiddle<4>(w, j, 2048, tw);
+        dft4(w);
+    }
+    __syncthreads();
+}
+
+}  // namespace
+
+// conj(DFT(w zero-padded to FFT_L)) of k correlation-order taps
+__global__ __launch_bounds__(FT) void k_conv_spectrum(const float* w, int k, float2* spec) {
+    __shared__ cf lds[FFT_L];
+    __shared__ cf tw[FFT_L];
+    const int t = threadIdx.x;
+    fill_twiddles(tw);
+    cf v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = t + FT * r;
+        v[r] = {i < k ? w[i] : 0.0f, 0.0f};
+    }
+    fft2048(v, lds, tw);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) spec[t + FT * h + 512 * r] = make_float2(v[4 * h + r].x, -v[4 * h + r].y);
+}
+
+__global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int adj, int out, int in, int base,
+                                                 double sigma, int gate) {
+    __shared__ cf lds[FFT_L];
+    __shared__ cf tw[FFT_L];
+    if ((int)blockIdx.x >= cl.nftiles) {   // initialisation tiles riding on the launch
+        const VecTile it = cl.init[blockIdx.x - cl.nftiles];
+        const InstDesc di = tb.inst[it.inst];
+        if (gate_ok(scal(di), gate)) init_tile<float>(tb, di, it, adj, out, in, base, sigma);
+        return;
+    }
+    const ConvTile tl = cl.ftiles[blockIdx.x];
+    const InstDesc d = tb.inst[tl.inst];
+    if (!gate_ok(scal(d), gate)) return;
+    const ConvBlock cb = cl.blocks[tl.blk];
+    int64_t n_out, n_in, off;
+    gptr<float> o;
+    gptr<const float> src;
+    const float2* spec;
+    if (!adj) {
+        n_out = cb.n_in + cb.k - 1;
+        n_in = cb.n_in;
+        off = -(cb.k - 1);
+        spec = (const float2*)cb.s_fwd;
+        o = yvec<float>(d, out) + cb.row0;
+        src = xvec<float>(d, in) + cb.col0;
+    } else {
+        n_out = cb.n_in;
+        n_in = cb.n_in + cb.k - 1;
+        off = 0;
+        spec = (const float2*)cb.s_adj;
+        o = xvec<float>(d, out) + cb.col0;
+        src = yvec<float>(d, in) + cb.row0;
+    }
+    const int t = threadIdx.x;
+    fill_twiddles(tw);
+    const int B = FFT_L - (int)cb.k + 1;   // outputs per window
+    const int64_t oa = tl.start, ob = tl.start + B;
+    cf v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int p = t + FT * r;
+        const int64_t ga = oa + off + p, gb = ob + off + p;
+        v[r] = {(ga >= 0 && ga < n_in) ? src[ga] : 0.0f, (gb >= 0 && gb < n_in) ? src[gb] : 0.0f};
+    }
+    fft2048(v, lds, tw);
+    // product with conj(DFT(w)), conjugated: the inverse is a forward transform
+    gptr<const float> sp = (gptr<const float>)spec;   // interleaved (re, im)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = t + FT * h + 512 * r;
+            const cf p = cmul(v[4 * h + r], cf{sp[2 * j], sp[2 * j + 1]});
+            lds[j] = {p.x, -p.y};
+        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = lds[t + FT * r];
+    __syncthreads();
+    fft2048(v, lds, tw);
+    // conj(result) / L: real part = window a, imaginary part = window b
+    const double s = sigma * cb.scale / (double)FFT_L;
+    const bool own = (cb.own >> adj) & 1;
+    const int64_t g0 = adj ? cb.col0 : cb.row0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = t + FT * h + 512 * r;
+            if (j >= B) continue;
+            const double va = (double)v[4 * h + r].x, vb = -(double)v[4 * h + r].y;
+            const int64_t ia = oa + j, ib = ob + j;
+            if (own) {
+                if (ia < n_out) o[ia] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ia) + s * va);
+                if (ib < n_out) o[ib] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ib) + s * vb);
+            } else {
+                if (ia < n_out) o[ia] = (float)((double)o[ia] + s * va);
+                if (ib < n_out) o[ib] = (float)((double)o[ib] + s * vb);
+            }
+        }
+}
+
+void launch_conv_spectrum(const void* w, int64_t k, void* spec, hipStream_t st) {
+    k_conv_spectrum<<<1, FT, 0, st>>>((const float*)w, (int)k, (float2*)spec);
+}
+
+void launch_conv_fft(const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base, double sigma,
+                     int gate, hipStream_t st) {
+    const int grid = c.nftiles + c.ninit;
+    if (grid <= 0) return;
+    k_conv_fft<<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);
+}
+
+}  // namespace cgs

@@ -53,6 +53,7 @@ int validate_settings(const cgs_settings* s) {
         return fail(CGS_EINVAL, "bf16_phase1_digits must be in [0, 15]");
     if (s->normalize < 0 || s->normalize > 2) return fail(CGS_EINVAL, "normalize must be 0, 1 or 2");
     if (s->fused_max < 0 || s->fused_lone_max < 0) return fail(CGS_EINVAL, "fused_max, fused_lone_max must be >= 0");
+    if (s->conv_mfma < 0 || s->conv_mfma > 2) return fail(CGS_EINVAL, "conv_mfma must be 0, 1 or 2");
     return CGS_OK;
 }
 
@@ -83,7 +84,10 @@ size_t op_dev_bytes(const cgs_op& op, int precision) {
     const size_t sz = elem_bytes(precision);
     size_t tot = 0;
     for (const auto& b : op.blocks) {
-        if (b.kind == CGS_BLOCK_CONV) tot += 2 * align256(round_up(b.k, conv_r(precision)) * sz);
+        if (b.kind == CGS_BLOCK_CONV) {
+            tot += 2 * align256(round_up(b.k, conv_r(precision)) * sz);
+            if (work_prec(precision) == 1 && b.k <= FFT_KMAX) tot += 2 * align256((size_t)FFT_L * 8);
+        }
         if (b.kind == CGS_BLOCK_DENSE) {
             const size_t ld = dense_ld(b.cols), ldt = dense_ld(b.rows);
             tot += align256(b.rows * ld * sz) + align256(b.cols * ldt * sz);
@@ -278,6 +282,14 @@ int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hi
             cb.w_adj = p;
             launch_cast(prec, stg.dev + kpad, p, kpad, st);
             p += align256(kpad * sz);
+            if (prec == 1 && k <= FFT_KMAX) {   // spectra for the FFT engine
+                cb.s_fwd = p;
+                launch_conv_spectrum(cb.w_fwd, k, p, st);
+                p += align256((size_t)FFT_L * 8);
+                cb.s_adj = p;
+                launch_conv_spectrum(cb.w_adj, k, p, st);
+                p += align256((size_t)FFT_L * 8);
+            }
             CGS_HIP(hipStreamSynchronize(st));
         } else if (b.kind == CGS_BLOCK_DENSE) {
             DenseBlock& db = out->dense[di++];
@@ -399,6 +411,8 @@ void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im
             if (im.cfwd.size() <= j) {
                 im.cfwd.resize(j + 1);
                 im.cadj.resize(j + 1);
+                im.ffwd.resize(j + 1);
+                im.fadj.resize(j + 1);
             }
             const ConvBlock& cb = r.op->convs[j];
             const int32_t bi = (int32_t)im.cblk.size();
@@ -406,6 +420,13 @@ void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im
             const int64_t n_out = cb.n_in + cb.k - 1;
             for (int64_t s = 0; s < n_out; s += ct) im.cfwd[j].push_back(ConvTile{ii, bi, s});
             for (int64_t s = 0; s < cb.n_in; s += ct) im.cadj[j].push_back(ConvTile{ii, bi, s});
+            if (work_prec(precision) == 1 && cb.k <= FFT_KMAX) {
+                // FFT-engine tiles (the blocks that get spectra at upload): two
+                // windows of FFT_L - k + 1 outputs each
+                const int64_t w2 = 2 * (FFT_L - cb.k + 1);
+                for (int64_t s = 0; s < n_out; s += w2) im.ffwd[j].push_back(ConvTile{ii, bi, s});
+                for (int64_t s = 0; s < cb.n_in; s += w2) im.fadj[j].push_back(ConvTile{ii, bi, s});
+            }
         }
         for (size_t j = 0; j < r.op->dense.size(); ++j) {
             if (im.dfwd.size() <= j) {
@@ -432,6 +453,8 @@ size_t image_table_bytes(const TableImage& im) {
                vbytes(im.cblk) + vbytes(im.dblk);
     for (const auto& v : im.cfwd) t += vbytes(v);
     for (const auto& v : im.cadj) t += vbytes(v);
+    for (const auto& v : im.ffwd) t += vbytes(v);
+    for (const auto& v : im.fadj) t += vbytes(v);
     for (const auto& v : im.dfwd) t += vbytes(v);
     for (const auto& v : im.dadj) t += vbytes(v);
     t += vbytes(im.xt) + vbytes(im.yt);   // initialisation tiles folded into convolution launches
@@ -534,12 +557,30 @@ int Engine::build(const std::vector<InstRec>& r) {
         for (const ConvTile& t : v) kc = std::max(kc, std::min(kcmax, im.cblk[t.blk].kpad));
         return (int)kc;
     };
-    for (const auto& v : im.cfwd)
+    // the FFT engine can take a slot when every block in it has spectra
+    auto slot_fft = [&](const std::vector<ConvTile>& v) {
+        bool ok = !v.empty();
+        for (const ConvTile& t : v) ok = ok && im.cblk[t.blk].s_fwd != nullptr;
+        return ok ? 1 : 0;
+    };
+    for (size_t j = 0; j < im.cfwd.size(); ++j) {
+        const auto& v = im.cfwd[j];
+        const int fft = slot_fft(v);
+        const auto& fv = im.ffwd[j];
         cf.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(),
-                                slot_kc(v), nullptr, 0});
-    for (const auto& v : im.cadj)
+                                slot_kc(v), nullptr, 0,
+                                fft ? (const ConvTile*)put(fv.data(), fv.size() * sizeof(ConvTile)) : nullptr,
+                                fft ? (int)fv.size() : 0, fft});
+    }
+    for (size_t j = 0; j < im.cadj.size(); ++j) {
+        const auto& v = im.cadj[j];
+        const int fft = slot_fft(v);
+        const auto& fv = im.fadj[j];
         ca.push_back(ConvLaunch{(const ConvTile*)put(v.data(), v.size() * sizeof(ConvTile)), cbd, (int)v.size(),
-                                slot_kc(v), nullptr, 0});
+                                slot_kc(v), nullptr, 0,
+                                fft ? (const ConvTile*)put(fv.data(), fv.size() * sizeof(ConvTile)) : nullptr,
+                                fft ? (int)fv.size() : 0, fft});
+    }
     // When every convolution owns its output range in a direction, the output
     // initialisation rides on the first convolution launch as extra
     // workgroups (one launch fewer per apply); tiles wholly inside an owned
@@ -598,9 +639,12 @@ char* Engine::yptr(int i, int kind) const {
     return d.base + REGION_HDR + ((size_t)NXV * d.nxs + (size_t)kind * d.nys) * elem_bytes(precision);
 }
 
-// Convolution tiles: matrix cores for FP32 (unless disabled), VALU otherwise.
+// Convolution engine for FP32 (conv_mfma): 1 matrix cores, 2 FFT (slots whose
+// blocks all have spectra; the matrix cores otherwise), 0 vector ALU; FP64
+// always on the vector ALU.
 void Engine::conv(const ConvLaunch& c, int adj, int out, int in, int base, double sigma, int gate) {
-    if (prec == 1 && st.conv_mfma) launch_conv_mfma(T, c, adj, out, in, base, sigma, gate, stream);
+    if (prec == 1 && st.conv_mfma == 2 && c.fft) launch_conv_fft(T, c, adj, out, in, base, sigma, gate, stream);
+    else if (prec == 1 && st.conv_mfma) launch_conv_mfma(T, c, adj, out, in, base, sigma, gate, stream);
     else launch_conv(prec, T, c, adj, out, in, base, sigma, gate, stream);
 }
 

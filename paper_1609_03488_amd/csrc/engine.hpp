@@ -129,6 +129,7 @@ struct TableImage {
     std::vector<IdBlock> ids;
     std::vector<ConvBlock> cblk;
     std::vector<std::vector<ConvTile>> cfwd, cadj;   // per conv slot
+    std::vector<std::vector<ConvTile>> ffwd, fadj;   // the same slots as FFT-engine tiles
     std::vector<DenseBlock> dblk;
     std::vector<std::vector<DenseTile>> dfwd, dadj;  // per dense slot
 };

@@ -20,6 +20,11 @@ struct ConvLaunch {
     // that the two kinds of workgroups write disjoint elements)
     const VecTile* init;
     int ninit;
+    // the same outputs as tiles of the FFT engine (two windows of FFT_L - k + 1
+    // outputs each); fft = 1 when every block of the launch has spectra
+    const ConvTile* ftiles;
+    int nftiles;
+    int fft;
 };
 // dynamic LDS bytes of the convolution kernel for a staging pass of kc taps
 size_t conv_smem_bytes(int prec, int kc);
@@ -41,6 +46,11 @@ void launch_conv_mfma(const Tables& t, const ConvLaunch& c, int adj, int out, in
                       double sigma,
                       int gate, hipStream_t st);
 size_t conv_mfma_smem_bytes(int kc);
+// FP32 only: the same convolution by FFT (overlap-save; conv_fft.hip), and the
+// conj(DFT) of k taps zero-padded to FFT_L points that it multiplies by
+void launch_conv_fft(const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base,
+                     double sigma, int gate, hipStream_t st);
+void launch_conv_spectrum(const void* w, int64_t k, void* spec, hipStream_t st);
 // out += sigma * scale * a (or a^T) * in for every dense tile.
 void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int out, int in,
                  double sigma, int gate, hipStream_t st);

@@ -33,15 +33,21 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def test_deconv_n1M_k1025_fp32():
+@pytest.mark.parametrize("engine", [1, 2, "autotune"], ids=["mfma", "fft", "autotune"])
+def test_deconv_n1M_k1025_fp32(engine):
+    """The benchmark solve on each FP32 convolution engine (and the one the
+    autotuner picks, as bench.py runs it)."""
     import torch
     cfg = w.workload("deconv_n1M_k1025")
-    _say(cfg["name"])
+    _say(cfg["name"], engine)
     d = w.make_deconv(cfg)
     pr = P.deconv_problem(d["c"], d["b"])
-    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10)
+    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"], check_every=10,
+                         conv_mfma=1 if engine == "autotune" else engine)
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=torch.cuda.Stream())
     s.set_data(0, pr.b, pr.c)
+    if engine == "autotune":
+        s.autotune(reps=5)
     info = s.solve()[0]
     assert info["status"] == P.SOLVED, info
     x, y, sl = s.solution(0)

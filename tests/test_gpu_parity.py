@@ -80,16 +80,46 @@ def _abs_bound(prog, v, adj):
                            [v[2 * n] + v[-1]]])
 
 
+FFT_L = 2048
+
+
+def _fft_term(prog, v, adj, D, E):
+    """Normwise rounding term of the FFT convolution engine for every output:
+    an FP32 transform of L points (forward and inverse, about 3 flops per
+    stage and value) perturbs the circular correlation by at most
+    ~ c log2(L) u ||W||_inf ||u_window||_2 with ||W||_inf <= ||w||_1; c = 12 is
+    generous.  Two windows share one complex transform, so the window norm is
+    that of both (sqrt 2 times the largest length-L window of the input)."""
+    if prog.family not in ("deconv", "lasso_conv"):
+        return 0.0
+    n, c = prog.data["n"], prog.data["c"]
+    k = c.shape[0]
+    scale = 1.0 if prog.family == "deconv" else 2.0
+    if not adj:
+        src, dsc = (E * v)[:n], D[-(n + k - 1):].max() if prog.family == "deconv" else D[2 * n + 1:2 * n + 1 + n + k - 1].max()
+        cin = src
+    else:
+        r0 = n + 1 if prog.family == "deconv" else 2 * n + 1
+        cin = (D * v)[r0:r0 + n + k - 1]
+        dsc = E[:n].max()
+    sq = np.concatenate([[0.0], np.cumsum(cin * cin)])
+    L = min(FFT_L, cin.shape[0])
+    win = np.sqrt(np.max(sq[L:] - sq[:-L])) if cin.shape[0] >= L else np.sqrt(sq[-1])
+    return 12 * np.log2(FFT_L) * 2.0 ** -24 * scale * dsc * np.abs(c).sum() * np.sqrt(2) * win
+
+
 @pytest.mark.parametrize("norm", [0, 2], ids=["given", "equilibrated"])
-@pytest.mark.parametrize("prec,mfma", [(P.FP64, 0), (P.FP32, 0), (P.FP32, 1)],
-                         ids=["fp64", "fp32-valu", "fp32-mfma"])
+@pytest.mark.parametrize("prec,mfma", [(P.FP64, 0), (P.FP32, 0), (P.FP32, 1), (P.FP32, 2)],
+                         ids=["fp64", "fp32-valu", "fp32-mfma", "fp32-fft"])
 @pytest.mark.parametrize("idx", range(len(CASES)))
 def test_forward_and_adjoint_apply(idx, prec, mfma, norm):
     """Elementwise: |dev - ref| <= (K + 4) u sum_j |a_ij||v_j|, with u the unit
     roundoff of the working precision and K the number of terms accumulated in
     that precision (convolution taps; the dense block accumulates in FP64).
-    FP32 convolutions run on the vector ALU or on the matrix cores.  With
-    equilibration the device applies D A E, the oracle's scaled operator."""
+    FP32 convolutions run on the vector ALU or on the matrix cores; on the FFT
+    engine the convolution's rounding is normwise per window and its bound is
+    added (_fft_term).  With equilibration the device applies D A E, the
+    oracle's scaled operator."""
     name, pr, prog = CASES[idx]
     _say("apply", name, prec, "mfma" if mfma else "valu", "norm" if norm else "given")
     s = _solver(pr, prec, conv_mfma=mfma, normalize=norm)
@@ -110,10 +140,13 @@ def test_forward_and_adjoint_apply(idx, prec, mfma, norm):
     # |D A E| |v| = D (|A| (E |v|))
     bf = D * _abs_bound(prog, E * z, False)
     ba = E * _abs_bound(prog, D * y, True)
-    assert np.all(np.abs(az - ref_az) <= (K + 4) * u * bf + 1e-300)
-    assert np.all(np.abs(aty - ref_aty) <= (K + 4) * u * ba + 1e-300)
+    tf = _fft_term(prog, z, False, D, E) if mfma == 2 else 0.0
+    ta = _fft_term(prog, y, True, D, E) if mfma == 2 else 0.0
+    assert np.all(np.abs(az - ref_az) <= (K + 4) * u * bf + tf + 1e-300)
+    assert np.all(np.abs(aty - ref_aty) <= (K + 4) * u * ba + ta + 1e-300)
     # adjoint identity on the device results
-    assert abs(az @ y - z @ aty) <= 4 * (K + 4) * u * (bf @ np.abs(y) + ba @ np.abs(z))
+    assert abs(az @ y - z @ aty) <= (4 * (K + 4) * u * (bf @ np.abs(y) + ba @ np.abs(z)) +
+                                     tf * np.abs(y).sum() + ta * np.abs(z).sum())
 
 
 def test_identity_kernel_conv_is_exact():
@@ -129,12 +162,13 @@ def test_identity_kernel_conv_is_exact():
 
 # ----------------------------------------------------------------- a4: CG
 
-@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+@pytest.mark.parametrize("prec,engine", [(P.FP64, 0), (P.FP32, 1), (P.FP32, 2)],
+                         ids=["fp64", "fp32-mfma", "fp32-fft"])
 @pytest.mark.parametrize("idx", range(len(CASES)))
-def test_cg_matches_direct_solve(idx, prec):
+def test_cg_matches_direct_solve(idx, prec, engine):
     name, pr, prog = CASES[idx]
-    _say("cg", name, prec)
-    s = _solver(pr, prec)
+    _say("cg", name, prec, engine)
+    s = _solver(pr, prec, conv_mfma=engine)
     rng = np.random.default_rng(100 + idx)
     r = rng.standard_normal(prog.n)
     tol = 1e-12 if prec == P.FP64 else 1e-6
@@ -243,10 +277,12 @@ def _objective(prog, x):
 
 
 @pytest.mark.parametrize("fused", [0, 65536], ids=["multikernel", "fused"])
-@pytest.mark.parametrize("idx,prec,eps", [(0, P.FP64, 1e-4), (0, P.FP32, 1e-4),
-                                           (1, P.FP64, 1e-6), (1, P.FP32, 1e-5),
-                                           (3, P.FP64, 1e-4), (3, P.FP32, 1e-4)])
-def test_solve_matches_oracle(idx, prec, eps, fused):
+@pytest.mark.parametrize("idx,prec,eps,engine", [(0, P.FP64, 1e-4, 0), (0, P.FP32, 1e-4, 1),
+                                                  (0, P.FP32, 1e-4, 2),
+                                                  (1, P.FP64, 1e-6, 0), (1, P.FP32, 1e-5, 1),
+                                                  (3, P.FP64, 1e-4, 0), (3, P.FP32, 1e-4, 1),
+                                                  (3, P.FP32, 1e-4, 2)])
+def test_solve_matches_oracle(idx, prec, eps, engine, fused):
     """Same method, same tolerance: the natural objective of the GPU solution is
     within 1e-4 (relative) of the oracle's, and the GPU point's residuals,
     recomputed in FP64, meet the tolerance.  At a 1e-4 stop the lasso's
@@ -254,8 +290,8 @@ def test_solve_matches_oracle(idx, prec, eps, fused):
     between the FP32 and FP64 stopping points), so its FP32 case stops at 1e-5;
     the deconvolution's FP32 and FP64 trajectories stay together at 1e-4."""
     name, pr, prog = ITER_CASES[idx]
-    _say("solve", name, prec, eps, fused)
-    s = _solver(pr, prec, eps=eps, check_every=10, fused_max=fused)
+    _say("solve", name, prec, eps, engine, fused)
+    s = _solver(pr, prec, eps=eps, check_every=10, fused_max=fused, conv_mfma=engine)
     s.set_data(0, pr.b, pr.c)
     info = s.solve()[0]
     assert info["status"] == P.SOLVED, info
@@ -474,11 +510,13 @@ def test_autotune_keeps_results_within_bounds():
     _say("autotune conv", name)
     s = _solver(pr, P.FP32, normalize=0)
     ch = s.autotune(reps=3)
-    assert ch["conv_mfma"] in (0, 1) and ch["gemm_target_wgs"] == -1
+    assert ch["conv_mfma"] in (0, 1, 2) and ch["gemm_target_wgs"] == -1
     rng = np.random.default_rng(5)
     z = rng.standard_normal(prog.n)
     u, K = 2.0 ** -24, prog.data["k"] + 4
-    assert np.all(np.abs(s.apply(z) - prog.A(z)) <= (K + 4) * u * _abs_bound(prog, z, False))
+    one_m, one_n = np.ones(prog.m), np.ones(prog.n)
+    tf = _fft_term(prog, z, False, one_m, one_n) if ch["conv_mfma"] == 2 else 0.0
+    assert np.all(np.abs(s.apply(z) - prog.A(z)) <= (K + 4) * u * _abs_bound(prog, z, False) + tf)
     _say("autotune gemm")
     A, prs, progs = _lasso_batch(300, 700, 37, 41)
     s = _solver(prs[0], P.BF16, batch=37, normalize=0)
