@@ -98,7 +98,14 @@ def run_deconv(args, cfg):
     s.set_data(0, pr.b, pr.c)
     log(f"workspace {s.workspace_bytes / 2**20:.1f} MiB")
     engine = 1 if prec == P.FP32 else 0
-    if prec == P.FP32 and not args.no_autotune:
+    if prec == P.FP32 and args.conv_engine is not None:
+        engine = args.conv_engine
+        s.close()
+        st.conv_mfma = engine
+        s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
+        s.set_data(0, pr.b, pr.c)
+        log(f"convolution {ENGINE_NAMES[engine]} (fixed)")
+    elif prec == P.FP32 and not args.no_autotune:
         engine = s.autotune(reps=10)["conv_mfma"]
         log(f"autotune: convolution {ENGINE_NAMES[engine]}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
@@ -594,6 +601,9 @@ def main():
                          "the CG systems), 2 for the dense lasso blocks")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel choices instead of timing the candidates")
+    ap.add_argument("--conv-engine", type=int, default=None, choices=(0, 1, 2),
+                    help="FP32 convolution engine without autotuning (0 vector ALU, 1 matrix "
+                         "cores, 2 FFT); for profiling runs of one engine")
     ap.add_argument("--max-iters", type=int, default=None,
                     help="cap on ADMM iterations (profiling runs; the JSON then says so)")
     ap.add_argument("--copy-calibration", type=int, default=0,
