@@ -522,3 +522,22 @@ def test_solution_independent_of_equilibration(family):
         assert np.isclose(rp, r.res_pri, rtol=1e-6, atol=1e-15)
         assert np.isclose(rd, r.res_dual, rtol=1e-6, atol=1e-15)
         assert max(rp, rd, gap) <= 1e-9
+
+
+def test_jacobi_diagonal_is_block_constant():
+    """Why the CG has no Jacobi preconditioner: diag(I + A^T A) of the
+    canonical forms is constant on every block for convolution and identity
+    blocks (each column of a full convolution holds the whole kernel), and for
+    the dense lasso block its extreme ratio is close to 1 (the squared column
+    norms of an m x n N(0, 1/m) matrix spread by sqrt(2/m))."""
+    d = w.deconv_instance(50, 9, 2.0, 0.2, 1e-4, 5)
+    for prog in (o.deconv_program(d["c"], d["b"]),
+                 o.conv_lasso_program(d["c"], d["b"], 0.1)):
+        A = prog.explicit()
+        diag = 1.0 + (A * A).sum(axis=0)
+        for _, _, c0, cols in prog.blocks:
+            blk = diag[c0:c0 + cols]
+            assert np.ptp(blk) <= 1e-12 * blk.max()
+    A = w.lasso_matrix(5000, 10000, 1003)
+    dx = 3.0 + 4.0 * (A * A).sum(axis=0)
+    assert dx.max() / dx.min() < 1.15
