@@ -105,6 +105,10 @@ struct InstDesc {
     int32_t db0, db1;    // dense-block range (Tables::dblk)
     int32_t fused;       // 1: whole ADMM steps run in one workgroup (k_fused)
     int32_t pad_;
+    // partials of CG steps folded into the A^T convolution launch (Tables::cpart
+    // indices): the instance's transform workgroups [cp0, cp1) and
+    // initialisation workgroups [ip0, ip1) of that launch
+    int32_t cp0, cp1, ip0, ip1;
 };
 
 // A tile of an X or Y vector: `len` elements from instance-local `start`.
@@ -187,6 +191,7 @@ struct Tables {
     const struct DenseBlock* dblk;
     double* xpart;       // 4 per X tile
     double* ypart;       // 4 per Y tile
+    double* cpart;       // 4 per workgroup of the A^T convolution launch (folded CG steps)
     int nx_tiles, ny_tiles, nseg, ninst;
 };
 

@@ -119,6 +119,16 @@ DEVI void fft2048(cf* v, cf* lds, const cf* tw) {
     __syncthreads();
 }
 
+// The workgroup's partials of a folded CG step (every thread calls this).
+DEVI void fold_partials(double* part, const Fold4& f, double* red) {
+    double v[4] = {f.a, f.b, f.c, f.d};
+    block_sum4<FT>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) part[4 * (int64_t)blockIdx.x + j] = v[j];
+    }
+}
+
 }  // namespace
 
 // conj(DFT(w zero-padded to FFT_L)) of k correlation-order taps
@@ -140,19 +150,25 @@ __global__ __launch_bounds__(FT) void k_conv_spectrum(const float* w, int k, flo
         for (int r = 0; r < 4; ++r) spec[t + FT * h + 512 * r] = make_float2(v[4 * h + r].x, -v[4 * h + r].y);
 }
 
+template <int FOLD>
 __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int adj, int out, int in, int base,
                                                  double sigma, int gate) {
     __shared__ cf lds[FFT_L];
     __shared__ cf tw[FFT_L];
+    __shared__ double red[4 * (FT / 64)];
+    Fold4 f{0.0, 0.0, 0.0, 0.0};
     if ((int)blockIdx.x >= cl.nftiles) {   // initialisation tiles riding on the launch
         const VecTile it = cl.init[blockIdx.x - cl.nftiles];
         const InstDesc di = tb.inst[it.inst];
-        if (gate_ok(scal(di), gate)) init_tile<float>(tb, di, it, adj, out, in, base, sigma);
+        if (!gate_ok(scal(di), gate)) return;
+        init_tile<float>(tb, di, it, adj, out, in, base, sigma, FOLD, cl.fr, cl.fp, cl.fq, f);
+        if (FOLD) fold_partials(cl.part, f, red);
         return;
     }
     const ConvTile tl = cl.ftiles[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
     if (!gate_ok(scal(d), gate)) return;
+    if (FOLD == 2 && (int)blockIdx.x == d.cp0 && threadIdx.x == 0) scal(d)[SC_CGRUN] = (double)cl.fit;
     const ConvBlock cb = cl.blocks[tl.blk];
     int64_t n_out, n_in, off;
     gptr<float> o;
@@ -213,6 +229,15 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
             const double va = (double)v[4 * h + r].x, vb = -(double)v[4 * h + r].y;
             const int64_t ia = oa + j, ib = ob + j;
             if (own) {
+                if (FOLD) {   // (the launch owns every X element)
+                    if (ia < n_out)
+                        fold_elem<float>(d, FOLD, cl.fr, cl.fp, cl.fq, out, g0 + ia,
+                                         owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ia) + s * va, f);
+                    if (ib < n_out)
+                        fold_elem<float>(d, FOLD, cl.fr, cl.fp, cl.fq, out, g0 + ib,
+                                         owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ib) + s * vb, f);
+                    continue;
+                }
                 if (ia < n_out) o[ia] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ia) + s * va);
                 if (ib < n_out) o[ib] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ib) + s * vb);
             } else {
@@ -220,6 +245,7 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
                 if (ib < n_out) o[ib] = (float)((double)o[ib] + s * vb);
             }
         }
+    if (FOLD) fold_partials(cl.part, f, red);
 }
 
 void launch_conv_spectrum(const void* w, int64_t k, void* spec, hipStream_t st) {
@@ -230,7 +256,9 @@ void launch_conv_fft(const Tables& t, const ConvLaunch& c, int adj, int out, int
                      int gate, hipStream_t st) {
     const int grid = c.nftiles + c.ninit;
     if (grid <= 0) return;
-    k_conv_fft<<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);
+    if (c.fold == 1) k_conv_fft<1><<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);
+    else if (c.fold == 2) k_conv_fft<2><<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);
+    else k_conv_fft<0><<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);
 }
 
 }  // namespace cgs

@@ -132,6 +132,27 @@ DEVI void inst_xsum4(const Tables& tb, const InstDesc& d, double (&s)[4], double
     block_sum4<VEC_NT>(s, sh);
 }
 
+// The same over the partials of a CG step folded into the instance's A^T
+// convolution launch: its transform workgroups, then its initialisation ones.
+DEVI void inst_csum4(const Tables& tb, const InstDesc& d, double (&s)[4], double* sh) {
+    s[0] = s[1] = s[2] = s[3] = 0.0;
+    for (int i = d.cp0 + (int)threadIdx.x; i < d.cp1; i += VEC_NT) {
+        const double* pp = tb.cpart + 4 * (int64_t)i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) s[j] += pp[j];
+    }
+    double u[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = d.ip0 + (int)threadIdx.x; i < d.ip1; i += VEC_NT) {
+        const double* pp = tb.cpart + 4 * (int64_t)i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] += pp[j];
+    }
+    block_sum4<VEC_NT>(s, sh);
+    block_sum4<VEC_NT>(u, sh);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] += u[j];
+}
+
 // The same for the instance's Y-tile partials.
 DEVI double inst_ysum(const Tables& tb, const InstDesc& d, int j, double* sh) {
     const double s = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, j, sh);
@@ -288,9 +309,40 @@ DEVI double owned_init(const InstDesc& d, const IdBlock* ids, int adj, int out, 
 // against owned ranges; an owned range inside the tile is skipped element by
 // element).  Convolution and dense blocks that do not own their range then
 // accumulate into these values.
+// Four partial sums of a CG step folded into an A^T launch.
+struct Fold4 {
+    double a, b, c, d;
+};
+
+// The CG work folded into an A^T launch for X element g whose apply output is
+// v (the arithmetic of k_cg_init and k_cg_dot):
+//   mode 1: h = v; r = h - x_fq, p = r are written (not h); a += r^2, b += h^2
+//   mode 2: q = v is written to `out`; a += p q, b += r^2, c += r q, d += q^2
+template <typename T>
+DEVI void fold_elem(const InstDesc& d, int mode, int fr, int fp, int fq, int out, int64_t g, double v,
+                    Fold4& f) {
+    if (mode == 1) {
+        const T h = (T)v;
+        const double hd = (double)h;
+        const T r = (T)(hd - (double)xvec<T>(d, fq)[g]);
+        xvec<T>(d, fr)[g] = r;
+        xvec<T>(d, fp)[g] = r;
+        f.a += (double)r * (double)r;
+        f.b += hd * hd;
+    } else {
+        const T q = (T)v;
+        xvec<T>(d, out)[g] = q;
+        const double pd = (double)xvec<T>(d, fp)[g], rd = (double)xvec<T>(d, fr)[g], qd = (double)q;
+        f.a = fma(pd, qd, f.a);
+        f.b = fma(rd, rd, f.b);
+        f.c = fma(rd, qd, f.c);
+        f.d = fma(qd, qd, f.d);
+    }
+}
+
 template <typename T>
 DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int adj, int out, int in,
-                    int base, double sigma) {
+                    int base, double sigma, int fold, int fr, int fp, int fq, Fold4& f) {
     gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
     gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
     gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
@@ -319,8 +371,15 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
             const int64_t c0 = adj ? ib.row0 : ib.col0;
             if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
         }
-        o[i] = (T)v;
+        if (fold) fold_elem<T>(d, fold, fr, fp, fq, out, i, v, f);
+        else o[i] = (T)v;
     }
+}
+template <typename T>
+DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int adj, int out, int in,
+                    int base, double sigma) {
+    Fold4 f{0.0, 0.0, 0.0, 0.0};
+    init_tile<T>(tb, d, tl, adj, out, in, base, sigma, 0, 0, 0, 0, f);
 }
 
 // relaxed point minus v for a Y entry

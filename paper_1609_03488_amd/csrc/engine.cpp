@@ -462,8 +462,10 @@ size_t image_table_bytes(const TableImage& im) {
 }
 
 size_t image_work_bytes(const TableImage& im) {
+    const size_t nfa = im.fadj.empty() ? 0 : im.fadj[0].size();
     return align256(4 * im.xt.size() * 8) + align256(4 * im.yt.size() * 8) +
            align256(2 * im.seg.size() * 8) + align256(im.seg.size() * 4) +
+           align256(4 * (nfa + im.xt.size()) * 8) +
            align256(im.inst.size() * NSC * 8) + 256;
 }
 
@@ -529,6 +531,55 @@ int Engine::build(const std::vector<InstRec>& r) {
         d.fused = (st.fused_max > 0 && !use_gemm && d.n + d.m <= lim && dense <= FUSED_DENSE_MAX) ? 1 : 0;
         (d.fused ? n_fused : n_multi) += 1;
     }
+    // When every convolution owns its output range in a direction, the output
+    // initialisation rides on the first convolution launch as extra
+    // workgroups (one launch fewer per apply); tiles wholly inside an owned
+    // range need no initialisation at all.
+    std::vector<VecTile> init_tiles[2];
+    for (int adj = 0; adj < 2; ++adj) {
+        fold_init[adj] = 0;
+        if ((adj ? im.cadj : im.cfwd).empty()) continue;
+        bool all = true;
+        for (const ConvBlock& cb : im.cblk) all = all && ((cb.own >> adj) & 1);
+        if (!all) continue;
+        for (const VecTile& t : adj ? im.xt : im.yt) {
+            const InstDesc& d = im.inst[t.inst];
+            bool covered = false;
+            for (int b = d.cb0; b < d.cb1 && !covered; ++b) {
+                const ConvBlock& cb = im.cblk[b];
+                const int64_t lo = adj ? cb.col0 : cb.row0;
+                const int64_t hi = lo + (adj ? cb.n_in : cb.n_in + cb.k - 1);
+                covered = lo <= t.start && t.start + t.len <= hi;
+            }
+            if (!covered) init_tiles[adj].push_back(t);
+        }
+        fold_init[adj] = 1;
+    }
+    // CG steps fold into the FFT engine's A^T launch when that launch (its
+    // transform workgroups and its initialisation workgroups) writes every X
+    // element: one convolution slot, all blocks owned and with spectra, no
+    // dense block.  Each instance's partials are then those of its transform
+    // workgroups and of its initialisation workgroups.
+    fold_cg = 0;
+    if (fold_init[1] && im.cadj.size() == 1 && im.dadj.empty() && !use_gemm && work_prec(precision) == 1) {
+        bool fft = !im.cadj[0].empty();
+        for (const ConvTile& t : im.cadj[0]) fft = fft && im.cblk[t.blk].k <= FFT_KMAX;
+        fold_cg = fft && !im.fadj.empty() ? 1 : 0;
+    }
+    for (InstDesc& d : im.inst) d.cp0 = d.cp1 = d.ip0 = d.ip1 = 0;
+    if (fold_cg) {
+        const int nft = (int)im.fadj[0].size();
+        for (int i = 0; i < nft; ++i) {
+            InstDesc& d = im.inst[im.fadj[0][i].inst];
+            if (d.cp1 == 0) d.cp0 = i;
+            d.cp1 = i + 1;
+        }
+        for (int i = 0; i < (int)init_tiles[1].size(); ++i) {
+            InstDesc& d = im.inst[init_tiles[1][i].inst];
+            if (d.ip1 == 0) d.ip0 = nft + i;
+            d.ip1 = nft + i + 1;
+        }
+    }
     const size_t tb = image_table_bytes(im), wb = image_work_bytes(im);
     if (tb > tab_cap || tb > tab_host_cap || wb > work_cap || (int)im.inst.size() > scal_host_cap)
         return fail(CGS_ENOMEM, "tile tables need %zu + %zu bytes (have %zu + %zu)", tb, wb, tab_cap, work_cap);
@@ -581,32 +632,11 @@ int Engine::build(const std::vector<InstRec>& r) {
                                 fft ? (const ConvTile*)put(fv.data(), fv.size() * sizeof(ConvTile)) : nullptr,
                                 fft ? (int)fv.size() : 0, fft});
     }
-    // When every convolution owns its output range in a direction, the output
-    // initialisation rides on the first convolution launch as extra
-    // workgroups (one launch fewer per apply); tiles wholly inside an owned
-    // range need no initialisation at all.
     for (int adj = 0; adj < 2; ++adj) {
         std::vector<ConvLaunch>& cl = adj ? ca : cf;
-        fold_init[adj] = 0;
-        if (cl.empty()) continue;
-        bool all = true;
-        for (const ConvBlock& cb : im.cblk) all = all && ((cb.own >> adj) & 1);
-        if (!all) continue;
-        std::vector<VecTile> init;
-        for (const VecTile& t : adj ? im.xt : im.yt) {
-            const InstDesc& d = im.inst[t.inst];
-            bool covered = false;
-            for (int b = d.cb0; b < d.cb1 && !covered; ++b) {
-                const ConvBlock& cb = im.cblk[b];
-                const int64_t lo = adj ? cb.col0 : cb.row0;
-                const int64_t hi = lo + (adj ? cb.n_in : cb.n_in + cb.k - 1);
-                covered = lo <= t.start && t.start + t.len <= hi;
-            }
-            if (!covered) init.push_back(t);
-        }
-        cl[0].init = (const VecTile*)put(init.data(), init.size() * sizeof(VecTile));
-        cl[0].ninit = (int)init.size();
-        fold_init[adj] = 1;
+        if (!fold_init[adj] || cl.empty()) continue;
+        cl[0].init = (const VecTile*)put(init_tiles[adj].data(), init_tiles[adj].size() * sizeof(VecTile));
+        cl[0].ninit = (int)init_tiles[adj].size();
     }
     for (const auto& v : im.dfwd) df.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
     for (const auto& v : im.dadj) da.push_back(DenseLaunch{(const DenseTile*)put(v.data(), v.size() * sizeof(DenseTile)), dbd, (int)v.size()});
@@ -617,6 +647,7 @@ int Engine::build(const std::vector<InstRec>& r) {
     T.ypart = (double*)w; w += align256(4 * im.yt.size() * 8);
     T.seg_val = (double*)w; w += align256(2 * im.seg.size() * 8);
     T.seg_cnt = (int*)w; w += align256(im.seg.size() * 4);
+    T.cpart = (double*)w; w += align256(4 * ((im.fadj.empty() ? 0 : im.fadj[0].size()) + im.xt.size()) * 8);
     gather_dev = (double*)w;
     if (!im.seg.empty()) CGS_HIP(hipMemsetAsync(T.seg_cnt, 0, im.seg.size() * 4, stream));
     T.nx_tiles = (int)im.xt.size();
@@ -665,6 +696,19 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
 // q = p + A^T (A p); alpha = rr/<p,q>; z += alpha p; r -= alpha q; beta; p = r + beta p.
 void Engine::cg_iter(int z, int gate, int cg_max, int track, int it) {
     apply(0, YT, XP, -1, 1.0, gate);
+    if (folded_cg()) {
+        // q = p + A^T (A p) with the dot partials and the iteration mark formed
+        // as each element of q is written (the work of k_cg_dot)
+        ConvLaunch c = ca[0];
+        c.fold = 2;
+        c.fr = XR;
+        c.fp = XP;
+        c.fit = it;
+        c.part = T.cpart;
+        conv(c, 1, XQ, YT, XP, 1.0, gate);
+        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1);
+        return;
+    }
     apply(1, XQ, YT, XP, 1.0, gate);
     launch_cg_dot(prec, T, XP, XQ, XR, it, gate, stream);
     launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream);
@@ -676,9 +720,22 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it) {
 // operator 1 + 2 * (CG iterations) times.
 void Engine::admm_step() {
     // w_y = u_y + v_s was written by the previous step's projection (or refresh)
-    apply(1, XH, YW, XU, -1.0, G_ADMM);                          // h = u_x - A^T w_y
-    launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
-                   st.cg_max_iters, G_ADMM, stream);             // r = h - K z
+    if (folded_cg()) {
+        // h = u_x - A^T w_y formed in the launch's epilogue, which writes
+        // r = h - K z and p = r (not h) and the CG start partials
+        ConvLaunch c = ca[0];
+        c.fold = 1;
+        c.fr = XR;
+        c.fp = XP;
+        c.fq = XK;
+        c.part = T.cpart;
+        conv(c, 1, XH, YW, XU, -1.0, G_ADMM);
+        launch_cg_start_folded(T, st.cg_tol, st.cg_rate, st.cg_floor, st.cg_max_iters, G_ADMM, stream);
+    } else {
+        apply(1, XH, YW, XU, -1.0, G_ADMM);                      // h = u_x - A^T w_y
+        launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
+                       st.cg_max_iters, G_ADMM, stream);         // r = h - K z
+    }
     for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i);
     launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; u~_tau, tau, kappa
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v

@@ -161,6 +161,9 @@ class Engine {
     double* gather_dev = nullptr;
     std::vector<ConvLaunch> cf, ca;
     int fold_init[2] = {0, 0};   // output initialisation rides on the first convolution launch
+    // CG start and CG products folded into the FFT engine's A^T launch: when
+    // that one launch writes every X element of every instance
+    int fold_cg = 0;
     std::vector<DenseLaunch> df, da;
     int cg_launch = 1;
     // fused path: one workgroup per instance runs whole steps (instances with
@@ -197,6 +200,8 @@ class Engine {
     void apply(int adj, int out, int in, int base, double sigma, int gate);
     void conv(const ConvLaunch& c, int adj, int out, int in, int base, double sigma, int gate);
     void cg_iter(int z, int gate, int cg_max, int track, int it);
+    // CG steps run folded into the A^T launch (FFT engine chosen and the tables allow it)
+    bool folded_cg() const { return fold_cg && prec == 1 && st.conv_mfma == 2 && !ca.empty() && ca[0].fft; }
     void admm_step();
     void fused_steps(int nsteps, int check);
     void check(int gate = G_CHECK);

@@ -206,14 +206,15 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
 // workgroup records alpha, beta, the counters and the run flag.
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q, int it,
-                                                      int cg_max, int gate, int track) {
+                                                      int cg_max, int gate, int track, int folded) {
     __shared__ double sh[4 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate) || sc[SC_CGRUN] != (double)it) return;
     double s[4];
-    inst_xsum4(tb, d, s, sh);
+    if (folded) inst_csum4(tb, d, s, sh);   // partials of the A^T launch
+    else inst_xsum4(tb, d, s, sh);          // partials of k_cg_dot
     const double pq = s[0], rr = s[1], rq = s[2], qq = s[3];
     const double al = rr / pq;
     const bool ok = pq > 0.0 && std::isfinite(al);
@@ -473,7 +474,12 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
     const bool use_x = true;
     const bool use_y = mode == FIN_RESID || mode == FIN_NORMS || mode == FIN_ETA;
     const int nslot = (mode == FIN_RESID) ? 3 : (mode == FIN_CG_INIT ? 2 : 1);
-    if (use_x) {
+    if (mode == FIN_CG_INIT && fa.i1) {
+        // CG start folded into the right-hand side's A^T launch: its transform
+        // workgroups' partials, then its initialisation workgroups'
+        x0 = sum_parts<VEC_NT>(tb.cpart, d.cp0, d.cp1, 0, sh) + sum_parts<VEC_NT>(tb.cpart, d.ip0, d.ip1, 0, sh);
+        x1 = sum_parts<VEC_NT>(tb.cpart, d.cp0, d.cp1, 1, sh) + sum_parts<VEC_NT>(tb.cpart, d.ip0, d.ip1, 1, sh);
+    } else if (use_x) {
         x0 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
         if (nslot > 1) x1 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 1, sh);
         if (nslot > 2) x2 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 2, sh);
@@ -768,15 +774,19 @@ void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h
                  floor_, cg_max, gate);
     k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_INIT, gate, FinArgs{zeta, rate, floor_, cg_max, 0});
 }
+void launch_cg_start_folded(const Tables& t, double zeta, double rate, double floor_, int cg_max, int gate,
+                            hipStream_t st) {
+    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_INIT, gate, FinArgs{zeta, rate, floor_, cg_max, 1});
+}
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, r, it, gate);
 }
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
-                      int gate, int track, hipStream_t st) {
+                      int gate, int track, hipStream_t st, int folded) {
     // the update's own gate is the phase test of the CG gate plus the mark of k_cg_dot
     const int g = gate == G_ADMM_CG ? G_ADMM : gate == G_SETUP_CG ? G_SETUP : G_ALL;
     CGS_DISPATCH(prec, k_cg_update, t.nx_tiles + (track ? t.ny_tiles : 0), VEC_NT, st, t, z, r, p, q,
-                 it, cg_max, g, track);
+                 it, cg_max, g, track, folded);
 }
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_wy, t.ny_tiles, VEC_NT, st, t, gate);

@@ -25,6 +25,17 @@ struct ConvLaunch {
     const ConvTile* ftiles;
     int nftiles;
     int fft;
+    // CG steps folded into an A^T launch of the FFT engine that writes every X
+    // element of every instance (fold != 0; partials in part[4 b + j] of
+    // workgroup b):
+    //   1 (CG start): the output is h; r = h - q and p = r are written instead
+    //     of h (kinds fr, fp, fq), partials ||r||^2, ||h||^2;
+    //   2 (CG products): the output is q = p + A^T A p; partials <p, q>,
+    //     ||r||^2, <r, q>, ||q||^2 (kinds fr, fp), and the iteration mark
+    //     fit in the instance's scalars (the role of k_cg_dot)
+    int fold;
+    int fr, fp, fq, fit;
+    double* part;
 };
 // dynamic LDS bytes of the convolution kernel for a staging pass of kc taps
 size_t conv_smem_bytes(int prec, int kc);
@@ -60,6 +71,10 @@ void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int o
 //       tol = ||h|| * max(floor, zeta / (k+1)^rate), CG active iff ||r|| > tol.
 void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h, int have_q,
                     double zeta, double rate, double floor, int cg_max, int gate, hipStream_t st);
+// the CG start when the right-hand side's A^T launch formed r, p and the
+// partials (ConvLaunch::fold = 1): tolerance and start flag only
+void launch_cg_start_folded(const Tables& t, double zeta, double rate, double floor_, int cg_max, int gate,
+                            hipStream_t st);
 // partials of <p, q>, ||r||^2, <r, q>, ||q||^2; marks iteration `it` as in progress
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int gate, hipStream_t st);
 // alpha = ||r||^2 / <p, q>; z += alpha p; r -= alpha q; beta = ||r'||^2 / ||r||^2
@@ -68,7 +83,8 @@ void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int g
 // track = 1: also K z += alpha q and A z += alpha (A p) (carried products)
 // `it`: CG iteration of the current loop (must match the preceding launch_cg_dot)
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
-                      int gate, int track, hipStream_t st);
+                      int gate, int track, hipStream_t st, int folded = 0);
+// (folded = 1: the partials come from the A^T launch of ConvLaunch::fold = 2)
 
 // ---- ADMM step pieces (Section V-B: subspace projection, then cone projection)
 // w_y = u_y + v_s
