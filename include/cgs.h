@@ -101,10 +101,18 @@ typedef struct {
                               max(eps, 10^-digits); the refinement phase (BF16 hi/lo
                               products, ~16 significant bits) then continues from its
                               state to eps with a fresh setup solve (default 3)       */
-    int32_t cg_adaptive;   /* 1: CG launches per step follow the most CG iterations any
-                              instance used in a step of the previous check interval
-                              (+1, capped at cg_max_iters); 0: always cg_max_iters.
-                              A server always uses 0 (results independent of the mix) */
+    int32_t cg_adaptive;   /* 1 (default): a check interval runs as many CG launches
+                              per step as the most CG iterations any instance used in
+                              a step of the previous interval (at least 1, at most
+                              cg_max_iters), starting from a copy of the state each
+                              step hands to the next.  When some step's CG would have
+                              gone on after its last launch, the interval is restored
+                              from that copy and run again with 2 L + 1 launches
+                              (capped), so results equal those of 0 bit for bit.  The
+                              copy takes 512 + (3 n' + 4 m') * element bytes of
+                              workspace per instance (n', m': n, m rounded up to 64).
+                              0: always cg_max_iters launches (no copy).  A server
+                              always uses 0                                           */
     int32_t fused_max;     /* instances with n + m <= fused_max run whole ADMM steps in
                               one workgroup each (one launch per check interval for
                               all of them, CG loop inside the kernel); larger ones
@@ -232,6 +240,11 @@ int cgs_solve(cgs_solver* s, cgs_info* info);
 /* Run exactly `iters` ADMM steps on every unfinished instance, with no
  * termination test (the setup solve runs first if needed). */
 int cgs_solver_iterate(cgs_solver* s, int32_t iters);
+/* Check intervals the solver has run since it was created, runs again
+ * included (rounds), and how many of them were runs again from an interval's
+ * start because a step needed more CG launches than the interval had (reruns,
+ * cg_adaptive = 1); either may be NULL. */
+int cgs_solver_rounds(cgs_solver* s, int64_t* rounds, int64_t* reruns);
 /* Primal-dual point (x = u_x/tau, y = u_y/tau, s = v_s/tau) of an instance, as
  * FP64 host arrays of n, m, m entries (any may be NULL). */
 int cgs_solver_get_solution(cgs_solver* s, int64_t inst, double* x, double* y, double* sl);

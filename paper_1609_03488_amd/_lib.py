@@ -87,6 +87,7 @@ _SIGS = {
     "cgs_solver_reset": (C.c_int, [_P, _I64]),
     "cgs_solve": (C.c_int, [_P, C.POINTER(Info)]),
     "cgs_solver_iterate": (C.c_int, [_P, C.c_int32]),
+    "cgs_solver_rounds": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cgs_solver_get_solution": (C.c_int, [_P, _I64, _DP, _DP, _DP]),
     "cgs_solver_get_state": (C.c_int, [_P, _I64, _DP, _DP, _DP, _DP]),
     "cgs_solver_set_state": (C.c_int, [_P, _I64, _DP, _DP, _DP, _DP]),
@@ -270,6 +271,12 @@ class Solver:
 
     def iterate(self, iters: int) -> None:
         _check(lib().cgs_solver_iterate(self._h, int(iters)))
+
+    def rounds(self):
+        """(check intervals run, intervals run again with more CG launches)."""
+        r, rr = C.c_int64(), C.c_int64()
+        _check(lib().cgs_solver_rounds(self._h, C.byref(r), C.byref(rr)))
+        return int(r.value), int(rr.value)
 
     def solution(self, inst: int = 0):
         x, y, s = np.empty(self.n), np.empty(self.m), np.empty(self.m)

@@ -37,7 +37,7 @@ int check_block(const cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int6
 
 // Device bytes of the solver: tables, reduction scratch, staging, operator data, regions.
 struct SolverLayout {
-    size_t tab = 0, work = 0, stg = 0, opb = 0, region = 0, total = 0;
+    size_t tab = 0, work = 0, stg = 0, opb = 0, region = 0, snap = 0, total = 0;
     size_t panel = 0, part = 0;          // BF16 GEMM panel (hi and lo) and split-K partials
     int64_t stg_doubles = 0;
 };
@@ -66,6 +66,7 @@ int solver_layout(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, con
     L->stg = cgs::align256((size_t)L->stg_doubles * sizeof(double));
     L->opb = cgs::align256(cgs::op_dev_bytes(*op, st->precision));
     L->region = cgs::region_bytes(op->n, op->m, st->precision);
+    L->snap = st->cg_adaptive ? cgs::snap_bytes(op->n, op->m, st->precision) : 0;
     if (st->precision == CGS_BF16) {
         for (const cgs::DenseBlock& db : shape.dense) {
             for (int adj = 0; adj < 2; ++adj) {
@@ -78,7 +79,8 @@ int solver_layout(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, con
             }
         }
     }
-    L->total = L->tab + L->work + L->stg + L->opb + 3 * L->panel + L->part + (size_t)batch * L->region;
+    L->total = L->tab + L->work + L->stg + L->opb + 3 * L->panel + L->part +
+               (size_t)batch * (L->region + L->snap);
     return CGS_OK;
 }
 
@@ -323,6 +325,9 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
         e.panel_stride = L.panel / sizeof(uint16_t);
         e.gemm_part = (float*)p; p += L.part;
     }
+    e.snap_dev = L.snap ? p : nullptr;
+    e.snap_cap = (size_t)batch * L.snap;
+    p += e.snap_cap;
     cgs::compute_scaling(*op, l, q, nq, st->normalize, &s->scl);
     CGS_TRY(cgs::op_upload(*op, st->precision, opdata, e.stg, e.stream, &s->opdev, s->scl.blk.data()));
     std::vector<cgs::InstRec> recs((size_t)batch);
@@ -555,6 +560,12 @@ static int solve_rounds(cgs_solver* s) {
     cgs::Engine& e = s->eng;
     for (;;) {
         CGS_TRY(e.fetch_scalars());
+        if (e.truncated()) {
+            // a step of the last interval needed more CG launches than it had
+            CGS_TRY(e.rollback());
+            continue;
+        }
+        e.spec_launch = 0;
         bool any = false;
         double min_it = 1e300;
         for (int i = 0; i < e.T.ninst; ++i) {
@@ -586,6 +597,13 @@ int cgs_solver_iterate(cgs_solver* s, int32_t iters) {
         for (int i = 0; i < iters; ++i) e.admm_step();
     CGS_HIP(hipGetLastError());
     CGS_HIP(hipStreamSynchronize(e.stream));
+    return CGS_OK;
+}
+
+int cgs_solver_rounds(cgs_solver* s, int64_t* rounds, int64_t* reruns) {
+    if (!s) return fail(CGS_EINVAL, "solver is null");
+    if (rounds) *rounds = s->eng.n_rounds;
+    if (reruns) *reruns = s->eng.n_reruns;
     return CGS_OK;
 }
 

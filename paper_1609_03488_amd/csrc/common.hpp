@@ -58,7 +58,9 @@ enum Scal : int {
     SC_RP, SC_RD, SC_GAP,                      // residuals at the last check
     SC_ACTIVE,                                 // 1 while the instance runs
     SC_PHASE,                                  // 0: setup pending, 1: iterating (one launch
-                                               // per kernel), 2: iterating (fused steps)
+                                               // per kernel), 2: iterating (fused steps),
+                                               // 3: suspended (a step needed more CG
+                                               // launches than its round had)
     SC_CGACT,                                  // 1 while CG of the instance runs
     SC_CGIT,                                   // CG iterations in the current solve
     SC_CGTOT,                                  // CG iterations since set_data
@@ -78,6 +80,10 @@ static_assert(NSC_USED <= NSC, "scalar slots");
 constexpr int NCNT = 64;     // int counters reserved per instance (256 bytes)
 constexpr int XY_ALIGN = 64; // elements
 constexpr int REGION_HDR = NSC * 8 + NCNT * 4;  // 512 bytes
+// vectors of that copy: u_x, z, K z and u_y, v_s, w_y, A z (every other vector
+// is either constant during the iteration or written before it is read in a step)
+constexpr int SNAP_X = 3;
+constexpr int SNAP_Y = 4;
 
 // ---------------------------------------------------------------- gates
 enum Gate : int {
@@ -109,6 +115,10 @@ struct InstDesc {
     // indices): the instance's transform workgroups [cp0, cp1) and
     // initialisation workgroups [ip0, ip1) of that launch
     int32_t cp0, cp1, ip0, ip1;
+    // copy of the state carried from one ADMM step to the next, taken at the
+    // start of a check interval run with fewer CG launches per step than the
+    // iteration limit (null: none): [header | SNAP_X vectors of nxs | SNAP_Y of nys]
+    char* snap;
 };
 
 // A tile of an X or Y vector: `len` elements from instance-local `start`.

@@ -80,6 +80,12 @@ size_t region_bytes(int64_t n, int64_t m, int precision) {
                     (size_t)NYV * round_up(m, XY_ALIGN) * sz);
 }
 
+size_t snap_bytes(int64_t n, int64_t m, int precision) {
+    const size_t sz = elem_bytes(precision);
+    return align256(REGION_HDR + (size_t)SNAP_X * round_up(n, XY_ALIGN) * sz +
+                    (size_t)SNAP_Y * round_up(m, XY_ALIGN) * sz);
+}
+
 size_t op_dev_bytes(const cgs_op& op, int precision) {
     const size_t sz = elem_bytes(precision);
     size_t tot = 0;
@@ -481,17 +487,17 @@ Engine::~Engine() {
 }
 
 void Engine::drop_graph() {
-    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    graph_exec = nullptr;
-    graph = nullptr;
-    graph_steps = -1;
-    graph_cg = -1;
+    for (CachedGraph& g : graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
 }
 
 // CG launches per step for the next check interval: the most CG iterations any
-// running instance used in a step of the last interval, plus two, within
-// [2, cg_max_iters]; fixed at cg_max_iters when adaptation is off.
+// running instance used in a step of the last interval, within [1,
+// cg_max_iters]; fixed at cg_max_iters when adaptation is off.  An interval
+// whose steps needed more is run again from its snapshot (Engine::rollback).
 void Engine::adapt_cg() {
     if (!st.cg_adaptive) {
         cg_launch = st.cg_max_iters;
@@ -502,7 +508,7 @@ void Engine::adapt_cg() {
         const double* sc = scalars(i);
         if (sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0) need = std::max(need, sc[SC_CGMAXLAST]);
     }
-    cg_launch = std::max(1, std::min(st.cg_max_iters, (int)need + 1));
+    cg_launch = std::max(1, std::min(st.cg_max_iters, (int)need));
 }
 
 int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles) {
@@ -580,6 +586,26 @@ int Engine::build(const std::vector<InstRec>& r) {
             d.ip1 = nft + i + 1;
         }
     }
+    // copies of the carried state for check intervals run with fewer CG
+    // launches per step than the iteration limit: one per instance of the
+    // one-launch-per-kernel path, packed into the snapshot area (none when
+    // they do not all fit)
+    {
+        size_t need = 0;
+        for (const InstDesc& d : im.inst)
+            if (!d.fused) need += snap_bytes(d.n, d.m, precision);
+        const bool fit = snap_dev != nullptr && need <= snap_cap;
+        size_t o = 0;
+        for (InstDesc& d : im.inst) {
+            d.snap = nullptr;
+            if (fit && !d.fused) {
+                d.snap = snap_dev + o;
+                o += snap_bytes(d.n, d.m, precision);
+            }
+        }
+        snap_ok = fit && n_multi > 0 ? 1 : 0;
+    }
+    spec_launch = 0;
     const size_t tb = image_table_bytes(im), wb = image_work_bytes(im);
     if (tb > tab_cap || tb > tab_host_cap || wb > work_cap || (int)im.inst.size() > scal_host_cap)
         return fail(CGS_ENOMEM, "tile tables need %zu + %zu bytes (have %zu + %zu)", tb, wb, tab_cap, work_cap);
@@ -694,7 +720,7 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
 
 // One CG iteration of the Section IV-B listing on (I + A^T A):
 // q = p + A^T (A p); alpha = rr/<p,q>; z += alpha p; r -= alpha q; beta; p = r + beta p.
-void Engine::cg_iter(int z, int gate, int cg_max, int track, int it) {
+void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last) {
     apply(0, YT, XP, -1, 1.0, gate);
     if (folded_cg()) {
         // q = p + A^T (A p) with the dot partials and the iteration mark formed
@@ -706,12 +732,12 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it) {
         c.fit = it;
         c.part = T.cpart;
         conv(c, 1, XQ, YT, XP, 1.0, gate);
-        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1);
+        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last);
         return;
     }
     apply(1, XQ, YT, XP, 1.0, gate);
     launch_cg_dot(prec, T, XP, XQ, XR, it, gate, stream);
-    launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream);
+    launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 0, last);
 }
 
 // One ADMM step of the homogeneous self-dual embedding.  The CG warm start z
@@ -736,7 +762,8 @@ void Engine::admm_step() {
         launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
                        st.cg_max_iters, G_ADMM, stream);         // r = h - K z
     }
-    for (int i = 0; i < cg_launch; ++i) cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i);
+    for (int i = 0; i < cg_launch; ++i)
+        cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == cg_launch - 1);
     launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; u~_tau, tau, kappa
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
@@ -784,9 +811,11 @@ void Engine::fused_steps(int nsteps, int check) {
     launch_fused(prec, T, fa, stream);
 }
 
-int Engine::round(int nsteps) {
+int Engine::round(int nsteps, bool multi_only) {
     bool forked = false;
-    if (n_fused && n_multi && stream != nullptr) {
+    if (multi_only) {
+        // the fused instances' interval already ran
+    } else if (n_fused && n_multi && stream != nullptr) {
         // both paths in the round: the fused launch runs on the side stream
         // beside the other instances' kernels (they touch disjoint instance
         // regions and partial buffers) and the main stream waits for it
@@ -811,34 +840,82 @@ int Engine::round(int nsteps) {
         CGS_HIP(hipGetLastError());
         return CGS_OK;
     }
+    // Fewer CG launches per step than the iteration limit: the interval starts
+    // with a copy of the carried state, kept until the host has seen whether
+    // some step's CG would have gone on after its last launch.
+    const bool spec = st.cg_adaptive && snap_ok && cg_launch < st.cg_max_iters;
+    if (!multi_only && spec) {
+        spec_live.assign((size_t)T.ninst, 0);
+        for (int i = 0; i < T.ninst; ++i) {
+            const double* sc = scalars(i);
+            spec_live[(size_t)i] = !im.inst[(size_t)i].fused && sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0;
+        }
+    }
+    spec_launch = spec ? cg_launch : 0;
+    spec_nsteps = nsteps;
+    spec_now = spec;
+    ++n_rounds;
     // Capture and instantiation cost more than launching one round directly,
     // so a graph is captured only for tables that have already served a round
     // (a server rebuilds them whenever requests arrive or leave).
     const bool use_g = st.use_graph && stream != nullptr && nsteps == st.check_every &&
-                       (graph_exec || rounds_since_build >= 1);
+                       (!graphs.empty() || rounds_since_build >= 1);
     ++rounds_since_build;
     if (use_g) {
-        if (!graph_exec || graph_steps != nsteps || graph_cg != cg_launch) {
-            drop_graph();
+        CachedGraph* hit = nullptr;
+        for (CachedGraph& g : graphs)
+            if (g.steps == nsteps && g.cg == cg_launch && g.spec == (int)spec) hit = &g;
+        if (!hit) {
+            if (graphs.size() >= GRAPH_CACHE) {
+                size_t old = 0;
+                for (size_t j = 1; j < graphs.size(); ++j)
+                    if (graphs[j].used < graphs[old].used) old = j;
+                (void)hipGraphExecDestroy(graphs[old].exec);
+                (void)hipGraphDestroy(graphs[old].graph);
+                graphs.erase(graphs.begin() + (std::ptrdiff_t)old);
+            }
             CGS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            if (spec) launch_snapshot(prec, T, 0, stream);
             for (int i = 0; i < nsteps; ++i) admm_step();
             check();
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(stream, &g);
             if (e != hipSuccess) return fail(CGS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-            graph = g;
-            CGS_HIP(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0));
-            graph_steps = nsteps;
-            graph_cg = cg_launch;
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(CGS_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+            }
+            graphs.push_back(CachedGraph{nsteps, cg_launch, (int)spec, g, x, 0});
+            hit = &graphs.back();
         }
-        CGS_HIP(hipGraphLaunch(graph_exec, stream));
+        hit->used = n_rounds;
+        CGS_HIP(hipGraphLaunch(hit->exec, stream));
     } else {
+        if (spec) launch_snapshot(prec, T, 0, stream);
         for (int i = 0; i < nsteps; ++i) admm_step();
         check();
     }
+    spec_now = false;
     if (forked) CGS_HIP(hipStreamWaitEvent(stream, ev_join, 0));
     CGS_HIP(hipGetLastError());
     return CGS_OK;
+}
+
+bool Engine::truncated() const {
+    if (spec_launch <= 0) return false;
+    for (int i = 0; i < T.ninst; ++i)
+        if (spec_live[(size_t)i] && scalars(i)[SC_PHASE] == 3.0) return true;
+    return false;
+}
+
+int Engine::rollback() {
+    launch_snapshot(prec, T, 1, stream);
+    CGS_HIP(hipGetLastError());
+    ++n_reruns;
+    cg_launch = std::min(st.cg_max_iters, 2 * spec_launch + 1);
+    return round(spec_nsteps, true);
 }
 
 int Engine::fetch_scalars() {

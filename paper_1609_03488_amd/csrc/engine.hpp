@@ -108,6 +108,8 @@ int upload_raw(const Staging& stg, hipStream_t st, const void* src, size_t bytes
 
 // Bytes of one instance's region (scalars, counters, X and Y vectors).
 size_t region_bytes(int64_t n, int64_t m, int precision);
+// copy of an instance's carried state (InstDesc::snap)
+size_t snap_bytes(int64_t n, int64_t m, int precision);
 
 int upload_f64(const Staging& stg, hipStream_t st, const double* src, int64_t n, int prec,
                void* dst);
@@ -166,6 +168,15 @@ class Engine {
     int fold_cg = 0;
     std::vector<DenseLaunch> df, da;
     int cg_launch = 1;
+    // snapshot area for check intervals run with fewer CG launches per step
+    // than the iteration limit (InstDesc::snap), and the last such interval:
+    // its launches (0: the last round was not one), steps and the instances
+    // that were iterating when it began
+    char* snap_dev = nullptr; size_t snap_cap = 0;
+    int snap_ok = 0;
+    int spec_launch = 0, spec_nsteps = 0;
+    std::vector<char> spec_live;
+    int64_t n_rounds = 0, n_reruns = 0;
     // fused path: one workgroup per instance runs whole steps (instances with
     // n + m <= fused_max); the others take one launch per kernel
     int n_fused = 0, n_multi = 0;
@@ -184,10 +195,17 @@ class Engine {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_steps = -1;
-    int graph_cg = -1;
+    // instantiated check-interval graphs, by (steps, CG launches per step); the
+    // launch count moves between a few values over a solve
+    struct CachedGraph {
+        int steps, cg, spec;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        int64_t used;
+    };
+    std::vector<CachedGraph> graphs;
+    static constexpr size_t GRAPH_CACHE = 4;
+    bool spec_now = false;        // the round being enqueued records a step that needs more CG launches
     int rounds_since_build = 0;   // a graph is captured only once the tables have held a round
 
     ~Engine();
@@ -199,7 +217,8 @@ class Engine {
     // ---- device work (enqueue only)
     void apply(int adj, int out, int in, int base, double sigma, int gate);
     void conv(const ConvLaunch& c, int adj, int out, int in, int base, double sigma, int gate);
-    void cg_iter(int z, int gate, int cg_max, int track, int it);
+    // last = 1: the step's last CG launch (records a step that needed more)
+    void cg_iter(int z, int gate, int cg_max, int track, int it, int last = 0);
     // CG steps run folded into the A^T launch (FFT engine chosen and the tables allow it)
     bool folded_cg() const { return fold_cg && prec == 1 && st.conv_mfma == 2 && !ca.empty() && ca[0].fft; }
     void admm_step();
@@ -209,7 +228,14 @@ class Engine {
     void adapt_cg();
     // ---- host loops
     int setup();                  // instances with phase 0 (synchronises)
-    int round(int nsteps);        // nsteps ADMM steps + termination test (enqueue)
+    // nsteps ADMM steps + termination test (enqueue); reads scal_host, so it
+    // follows fetch_scalars.  multi_only: the one-launch-per-kernel instances only
+    int round(int nsteps, bool multi_only = false);
+    // after fetch_scalars: the last round ran fewer CG launches per step than
+    // some step of an instance needed
+    bool truncated() const;
+    // restore the snapshot of that round and run it again with more launches
+    int rollback();
     int fetch_scalars();          // gather per-instance scalars into scal_host (synchronises)
     const double* scalars(int i) const { return scal_host + (size_t)i * NSC; }
     int reset(int inst);          // inst < 0: all

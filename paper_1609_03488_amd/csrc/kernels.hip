@@ -206,7 +206,8 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
 // workgroup records alpha, beta, the counters and the run flag.
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q, int it,
-                                                      int cg_max, int gate, int track, int folded) {
+                                                      int cg_max, int gate, int track, int folded,
+                                                      int last) {
     __shared__ double sh[4 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
@@ -232,6 +233,11 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
             if (sc[SC_CGIT] > sc[SC_CGMAX]) sc[SC_CGMAX] = sc[SC_CGIT];
             if (gate == G_SETUP) sc[SC_SETUPIT] += 1.0;
         }
+        // the step's last CG launch, and CG would go on: the step needs more
+        // launches than the interval has.  The instance is suspended (phase 3:
+        // every later kernel of the interval skips it) until the host restores
+        // the interval's snapshot and runs the interval again.
+        if (last && more) sc[SC_PHASE] = 3.0;
         sc[SC_CGACT] = more ? 1.0 : 0.0;
     }
     if (!ok) return;
@@ -640,6 +646,37 @@ __global__ __launch_bounds__(VEC_NT) void k_copy(Tables tb, int is_y, int dst, i
     for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) o[i] = s[i];
 }
 
+// Copy of the carried state of every instance that runs one launch per kernel
+// (restore = 0: region -> copy; 1: copy -> region).  X tiles copy u_x, z, K z,
+// Y tiles u_y, v_s, w_y, A z; the first X tile's workgroup also copies the
+// header (scalars and counters).  Instances of the fused path, which runs
+// concurrently on another stream, and instances without a copy are left alone.
+template <typename T>
+__global__ __launch_bounds__(VEC_NT) void k_snapshot(Tables tb, int restore) {
+    const XYTile xt = xy_tile(tb);
+    const InstDesc d = tb.inst[xt.t.inst];
+    if (d.fused || d.snap == nullptr) return;
+    gptr<char> region = (gptr<char>)d.base;
+    gptr<char> copy = (gptr<char>)d.snap;
+    if (!xt.is_y && xt.index == d.xt0) {
+        gptr<const int64_t> hs = (gptr<const int64_t>)(restore ? copy : region);
+        gptr<int64_t> hd = (gptr<int64_t>)(restore ? region : copy);
+        for (int i = threadIdx.x; i < REGION_HDR / 8; i += VEC_NT) hd[i] = hs[i];
+    }
+    gptr<T> cx = (gptr<T>)(copy + REGION_HDR);
+    gptr<T> cy = cx + (int64_t)SNAP_X * d.nxs;
+    const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
+    const int nv = xt.is_y ? SNAP_Y : SNAP_X;
+    for (int v = 0; v < nv; ++v) {
+        gptr<T> live = xt.is_y ? yvec<T>(d, v == 0 ? YU : v == 1 ? YV : v == 2 ? YW : YA)
+                               : xvec<T>(d, v == 0 ? XU : v == 1 ? XZ : XK);
+        gptr<T> kept = xt.is_y ? cy + (int64_t)v * d.nys : cx + (int64_t)v * d.nxs;
+        gptr<T> dst = restore ? live : kept;
+        gptr<const T> src = restore ? kept : live;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) dst[i] = src[i];
+    }
+}
+
 // Points of the original problem (what 0: x, 1: y, 2: s; rays scaled by
 // -c^T x_ray or -b^T y_ray for certificates) or the raw iterate (3: u_x,
 // 4: u_y, 5: v_s) of the scaled problem.
@@ -782,11 +819,14 @@ void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int g
     CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, r, it, gate);
 }
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
-                      int gate, int track, hipStream_t st, int folded) {
+                      int gate, int track, hipStream_t st, int folded, int last) {
     // the update's own gate is the phase test of the CG gate plus the mark of k_cg_dot
     const int g = gate == G_ADMM_CG ? G_ADMM : gate == G_SETUP_CG ? G_SETUP : G_ALL;
     CGS_DISPATCH(prec, k_cg_update, t.nx_tiles + (track ? t.ny_tiles : 0), VEC_NT, st, t, z, r, p, q,
-                 it, cg_max, g, track, folded);
+                 it, cg_max, g, track, folded, last);
+}
+void launch_snapshot(int prec, const Tables& t, int restore, hipStream_t st) {
+    CGS_DISPATCH(prec, k_snapshot, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, restore);
 }
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_wy, t.ny_tiles, VEC_NT, st, t, gate);

@@ -83,8 +83,14 @@ void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int g
 // track = 1: also K z += alpha q and A z += alpha (A p) (carried products)
 // `it`: CG iteration of the current loop (must match the preceding launch_cg_dot)
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
-                      int gate, int track, hipStream_t st, int folded = 0);
-// (folded = 1: the partials come from the A^T launch of ConvLaunch::fold = 2)
+                      int gate, int track, hipStream_t st, int folded = 0, int last = 0);
+// (folded = 1: the partials come from the A^T launch of ConvLaunch::fold = 2;
+// last = 1: the step's last CG launch of a round run from a snapshot; when CG
+// would go on the instance is suspended, phase 3, for the host to run the
+// round again with more launches)
+// copy of the carried state of the instances on the one-launch-per-kernel path
+// (InstDesc::snap); restore = 1 copies it back
+void launch_snapshot(int prec, const Tables& t, int restore, hipStream_t st);
 
 // ---- ADMM step pieces (Section V-B: subspace projection, then cone projection)
 // w_y = u_y + v_s

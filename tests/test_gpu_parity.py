@@ -385,6 +385,45 @@ def test_batch_instances_equal_single_solves():
         np.testing.assert_array_equal(sb.solution(i)[0], s1.solution(0)[0])
 
 
+def _spec_cases():
+    d1 = w.deconv_instance(3000, 101, 15.0, 0.1, 1e-4, 11)
+    d2 = w.deconv_instance(20000, 1025, 150.0, 0.01, 1e-6, 13)
+    A = w.lasso_matrix(300, 900, 41)
+    d3 = w.lasso_instance(300, 900, 0.05, 1e-4, 4100, A=A, matrix_seed=41)
+    return [("deconv_n3000_k101", P.deconv_problem(d1["c"], d1["b"])),
+            ("deconv_n20000_k1025", P.deconv_problem(d2["c"], d2["b"])),
+            ("lasso_300x900", P.lasso_problem(A, d3["b"], d3["lam"]))]
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
+def test_predicted_cg_launches_equal_full_launches(prec):
+    """cg_adaptive = 1 runs each check interval with the previous interval's
+    most CG iterations per step as launches and runs an interval again from
+    its snapshot when a step needed more; the iterates must equal those of
+    cg_adaptive = 0 (cg_max_iters launches every step) bit for bit.  A fast
+    tightening CG tolerance (cg_rate 3) makes the per-step need grow, so some
+    interval is run again."""
+    reruns = 0
+    for name, pr in _spec_cases():
+        for rate in (1.5, 3.0):
+            _say("predicted cg launches", name, prec, rate)
+            out = {}
+            for ad in (0, 1):
+                s = _solver(pr, prec, eps=1e-5, check_every=10, fused_max=0, cg_rate=rate,
+                            cg_floor=1e-9, max_iters=3000, cg_adaptive=ad)
+                s.set_data(0, pr.b, pr.c)
+                info = s.solve()[0]
+                out[ad] = (info, s.solution(0), s.rounds())
+            i0, i1 = out[0][0], out[1][0]
+            assert (i0["status"], i0["iters"], i0["cg_iters"]) == (i1["status"], i1["iters"], i1["cg_iters"])
+            for a, b in zip(out[0][1], out[1][1]):
+                np.testing.assert_array_equal(a, b)
+            print("[case] rounds/reruns", name, rate, out[1][2], "iters", i1["iters"], "cg", i1["cg_iters"],
+                  flush=True)
+            reruns += out[1][2][1]
+    assert reruns > 0
+
+
 def test_server_result_same_alone_and_in_mix():
     _say("server alone vs mix")
     reqs = [w.deconv_instance(n, k, k / 7.0, 0.05, 1e-4, 4000 + n) for n, k in
