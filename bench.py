@@ -64,6 +64,9 @@ def timed_solves(s, steps, warmup, label):
         infos.append(s.solve())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if hasattr(s, "rounds"):
+        r0, r1 = s.rounds()
+        log(f"{label} check intervals since creation: {r0} ({r1} run again with more CG launches)")
     for i, inf in enumerate(infos):
         log(f"{label} step {i}: {inf[0]['status_name']} iters={inf[0]['iters']} cg={inf[0]['cg_iters']} "
             f"res=({inf[0]['res_pri']:.2e},{inf[0]['res_dual']:.2e},{inf[0]['gap']:.2e})")

@@ -112,7 +112,7 @@ struct InstDesc {
     int32_t fused;       // 1: whole ADMM steps run in one workgroup (k_fused)
     int32_t pad_;
     // partials of CG steps folded into the A^T convolution launch (Tables::cpart
-    // indices): the instance's transform workgroups [cp0, cp1) and
+    // and Tables::spart indices): the instance's transform workgroups [cp0, cp1) and
     // initialisation workgroups [ip0, ip1) of that launch
     int32_t cp0, cp1, ip0, ip1;
     // copy of the state carried from one ADMM step to the next, taken at the
@@ -201,7 +201,8 @@ struct Tables {
     const struct DenseBlock* dblk;
     double* xpart;       // 4 per X tile
     double* ypart;       // 4 per Y tile
-    double* cpart;       // 4 per workgroup of the A^T convolution launch (folded CG steps)
+    double* cpart;       // 4 per workgroup of the A^T convolution launch (folded CG products)
+    double* spart;       // the same for the right-hand side's A^T launch (folded CG start)
     int nx_tiles, ny_tiles, nseg, ninst;
 };
 

@@ -216,35 +216,146 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
     for (int r = 0; r < 8; ++r) v[r] = lds[t + FT * r];
     __syncthreads();
     fft2048(v, lds, tw);
-    // conj(result) / L: real part = window a, imaginary part = window b
+    // conj(result) / L: real part = window a, imaginary part = window b.
+    // Epilogue: every load of the thread's outputs (base, identity blocks,
+    // folded operands) is issued before its first store; element by element
+    // each load would wait for the previous element's stores, since they may
+    // alias as far as the compiler knows.  The additions keep the order of the
+    // element-wise form: (base + identity terms) + sum, then the fold.
     const double s = sigma * cb.scale / (double)FFT_L;
     const bool own = (cb.own >> adj) & 1;
     const int64_t g0 = adj ? cb.col0 : cb.row0;
+    bool id_hit = false;     // an identity block adds to the workgroup's outputs
+    for (int b = d.id0; b < d.id1; ++b) {
+        const IdBlock ib = tb.ids[b];
+        const int64_t r0 = adj ? ib.col0 : ib.row0;
+        id_hit = id_hit || (ib.len > 0 && r0 < g0 + oa + 2 * (int64_t)B && r0 + ib.len > g0 + oa);
+    }
+    if (FOLD == 0 && own && base < 0 && !id_hit) {
+        // nothing to load: the outputs are the sums alone
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = t + FT * h + 512 * r;
+                if (j >= B) continue;
+                const int64_t ia = oa + j, ib = ob + j;
+                if (ia < n_out) o[ia] = (float)(0.0 + s * (double)v[4 * h + r].x);
+                if (ib < n_out) o[ib] = (float)(0.0 + s * -(double)v[4 * h + r].y);
+            }
+        return;
+    }
+    constexpr int NE = 16;   // two windows x 8 values
+    int64_t gi[NE];          // block-local output index, -1: none
+    double res[NE];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+            const int e = 4 * h + r;
             const int j = t + FT * h + 512 * r;
-            if (j >= B) continue;
-            const double va = (double)v[4 * h + r].x, vb = -(double)v[4 * h + r].y;
             const int64_t ia = oa + j, ib = ob + j;
-            if (own) {
-                if (FOLD) {   // (the launch owns every X element)
-                    if (ia < n_out)
-                        fold_elem<float>(d, FOLD, cl.fr, cl.fp, cl.fq, out, g0 + ia,
-                                         owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ia) + s * va, f);
-                    if (ib < n_out)
-                        fold_elem<float>(d, FOLD, cl.fr, cl.fp, cl.fq, out, g0 + ib,
-                                         owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ib) + s * vb, f);
-                    continue;
-                }
-                if (ia < n_out) o[ia] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ia) + s * va);
-                if (ib < n_out) o[ib] = (float)(owned_init<float>(d, tb.ids, adj, out, in, base, sigma, g0 + ib) + s * vb);
-            } else {
-                if (ia < n_out) o[ia] = (float)((double)o[ia] + s * va);
-                if (ib < n_out) o[ib] = (float)((double)o[ib] + s * vb);
+            gi[2 * e] = (j < B && ia < n_out) ? ia : -1;
+            gi[2 * e + 1] = (j < B && ib < n_out) ? ib : -1;
+            res[2 * e] = (double)v[e].x;
+            res[2 * e + 1] = -(double)v[e].y;
+        }
+    if (!own) {
+        double old[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) old[e] = (double)o[gi[e] >= 0 ? gi[e] : 0];
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (gi[e] >= 0) o[gi[e]] = (float)(old[e] + s * res[e]);
+        return;
+    }
+    // base + identity blocks of the owned range
+    double bv[NE];
+    {
+        // (loads are unconditional, at the block's first element where the
+        // thread has no output, so that none sits behind a branch)
+        if (base >= 0) {
+            gptr<const float> bp = adj ? xvec<float>(d, base) : yvec<float>(d, base);
+            float l[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) l[e] = bp[g0 + (gi[e] >= 0 ? gi[e] : 0)];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) bv[e] = gi[e] >= 0 ? (double)l[e] : 0.0;
+        } else {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) bv[e] = 0.0;
+        }
+        gptr<const float> isrc = adj ? yvec<float>(d, in) : xvec<float>(d, in);
+        for (int b = d.id0; b < d.id1; ++b) {
+            const IdBlock ib = tb.ids[b];
+            const int64_t r0 = adj ? ib.col0 : ib.row0;
+            // blocks that miss the workgroup's outputs [oa, oa + 2B) issue no load
+            if (ib.len <= 0 || r0 >= g0 + oa + 2 * (int64_t)B || r0 + ib.len <= g0 + oa) continue;
+            const int64_t c0 = adj ? ib.row0 : ib.col0;
+            const double w = sigma * ib.scale;
+            float l[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int64_t g = g0 + gi[e];
+                const bool in_r = gi[e] >= 0 && g >= r0 && g < r0 + ib.len;
+                l[e] = isrc[in_r ? g - r0 + c0 : c0];
+            }
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int64_t g = g0 + gi[e];
+                if (gi[e] >= 0 && g >= r0 && g < r0 + ib.len) bv[e] += w * (double)l[e];
             }
         }
+    }
+    if (FOLD == 0) {
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            if (gi[e] >= 0) o[gi[e]] = (float)(bv[e] + s * res[e]);
+        return;
+    }
+    // (a folded launch owns every X element)
+    if (FOLD == 1) {
+        // h = value; r = h - K z, p = r written instead of h
+        gptr<const float> kz = xvec<float>(d, cl.fq);
+        float kv[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) kv[e] = kz[g0 + (gi[e] >= 0 ? gi[e] : 0)];
+        gptr<float> rv = xvec<float>(d, cl.fr);
+        gptr<float> pv = xvec<float>(d, cl.fp);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            if (gi[e] < 0) continue;
+            const float hv = (float)(bv[e] + s * res[e]);
+            const double hd = (double)hv;
+            const float rr = (float)(hd - (double)kv[e]);
+            rv[g0 + gi[e]] = rr;
+            pv[g0 + gi[e]] = rr;
+            f.a += (double)rr * (double)rr;
+            f.b += hd * hd;
+        }
+    } else {
+        // q = value; partials <p, q>, ||r||^2, <r, q>, ||q||^2
+        gptr<const float> pp = xvec<float>(d, cl.fp);
+        gptr<const float> rp = xvec<float>(d, cl.fr);
+        float pvv[NE], rvv[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            pvv[e] = pp[g0 + (gi[e] >= 0 ? gi[e] : 0)];
+            rvv[e] = rp[g0 + (gi[e] >= 0 ? gi[e] : 0)];
+        }
+        gptr<float> qo = xvec<float>(d, out);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            if (gi[e] < 0) continue;
+            const float q = (float)(bv[e] + s * res[e]);
+            qo[g0 + gi[e]] = q;
+            const double pd = (double)pvv[e], rd = (double)rvv[e], qd = (double)q;
+            f.a = fma(pd, qd, f.a);
+            f.b = fma(rd, rd, f.b);
+            f.c = fma(rd, qd, f.c);
+            f.d = fma(qd, qd, f.d);
+        }
+    }
     if (FOLD) fold_partials(cl.part, f, red);
 }
 

@@ -87,6 +87,29 @@ DEVI void block_sum4(double (&s)[4], double* sh) {
     __syncthreads();
 }
 
+// N sums at once, each in the order of block_sum4 (sh: N * NT / 64 doubles):
+// one barrier pair for all of them.
+template <int NT, int N>
+DEVI void block_sumN(double (&s)[N], double* sh) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[j] = wave_sum(s[j]);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) sh[j * (NT / 64) + w] = s[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        double r = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) r += sh[j * (NT / 64) + i];
+        s[j] = r;
+    }
+    __syncthreads();
+}
+
 // Fixed-order sum of partial slot j over tiles [t0, t1) (partials of the
 // previous kernel: the kernel boundary makes them visible).
 template <int NT>
@@ -133,24 +156,48 @@ DEVI void inst_xsum4(const Tables& tb, const InstDesc& d, double (&s)[4], double
 }
 
 // The same over the partials of a CG step folded into the instance's A^T
-// convolution launch: its transform workgroups, then its initialisation ones.
-DEVI void inst_csum4(const Tables& tb, const InstDesc& d, double (&s)[4], double* sh) {
-    s[0] = s[1] = s[2] = s[3] = 0.0;
+// convolution launch (Tables::cpart): its transform workgroups, then its
+// initialisation ones; with start, also slots 0 and 1 of the right-hand side
+// launch's partials (Tables::spart: ||r||^2, ||h||^2 of the CG start), all
+// loaded in the same pass (sh: 12 * VEC_NT / 64 doubles).
+DEVI void inst_csum4(const Tables& tb, const InstDesc& d, double (&s)[4], bool start, double& h0, double& h1,
+                     double* sh) {
+    double a[12];
+#pragma unroll
+    for (int j = 0; j < 12; ++j) a[j] = 0.0;
     for (int i = d.cp0 + (int)threadIdx.x; i < d.cp1; i += VEC_NT) {
         const double* pp = tb.cpart + 4 * (int64_t)i;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) s[j] += pp[j];
+        for (int j = 0; j < 4; ++j) a[j] += pp[j];
+        if (start) {
+            const double* qq = tb.spart + 4 * (int64_t)i;
+            a[4] += qq[0];
+            a[5] += qq[1];
+        }
     }
-    double u[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = d.ip0 + (int)threadIdx.x; i < d.ip1; i += VEC_NT) {
         const double* pp = tb.cpart + 4 * (int64_t)i;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) u[j] += pp[j];
+        for (int j = 0; j < 4; ++j) a[6 + j] += pp[j];
+        if (start) {
+            const double* qq = tb.spart + 4 * (int64_t)i;
+            a[10] += qq[0];
+            a[11] += qq[1];
+        }
     }
-    block_sum4<VEC_NT>(s, sh);
-    block_sum4<VEC_NT>(u, sh);
+    block_sumN<VEC_NT, 12>(a, sh);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s[j] += u[j];
+    for (int j = 0; j < 4; ++j) s[j] = a[j] + a[6 + j];
+    h0 = a[4] + a[10];
+    h1 = a[5] + a[11];
+}
+
+// CG stop threshold at ADMM step k (k = 0 in the setup solve):
+// ||h|| max(floor, zeta / (k+1)^rate)
+DEVI double cg_tolerance(double k, double hh, double zeta, double rate, double floor_) {
+    double rel = zeta > 0.0 ? zeta / pow(k + 1.0, rate) : 0.0;
+    rel = rel > floor_ ? rel : floor_;
+    return sqrt(hh) * rel;
 }
 
 // The same for the instance's Y-tile partials.

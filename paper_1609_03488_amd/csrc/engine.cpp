@@ -471,7 +471,7 @@ size_t image_work_bytes(const TableImage& im) {
     const size_t nfa = im.fadj.empty() ? 0 : im.fadj[0].size();
     return align256(4 * im.xt.size() * 8) + align256(4 * im.yt.size() * 8) +
            align256(2 * im.seg.size() * 8) + align256(im.seg.size() * 4) +
-           align256(4 * (nfa + im.xt.size()) * 8) +
+           2 * align256(4 * (nfa + im.xt.size()) * 8) +
            align256(im.inst.size() * NSC * 8) + 256;
 }
 
@@ -674,6 +674,7 @@ int Engine::build(const std::vector<InstRec>& r) {
     T.seg_val = (double*)w; w += align256(2 * im.seg.size() * 8);
     T.seg_cnt = (int*)w; w += align256(im.seg.size() * 4);
     T.cpart = (double*)w; w += align256(4 * ((im.fadj.empty() ? 0 : im.fadj[0].size()) + im.xt.size()) * 8);
+    T.spart = (double*)w; w += align256(4 * ((im.fadj.empty() ? 0 : im.fadj[0].size()) + im.xt.size()) * 8);
     gather_dev = (double*)w;
     if (!im.seg.empty()) CGS_HIP(hipMemsetAsync(T.seg_cnt, 0, im.seg.size() * 4, stream));
     T.nx_tiles = (int)im.xt.size();
@@ -720,7 +721,24 @@ void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
 
 // One CG iteration of the Section IV-B listing on (I + A^T A):
 // q = p + A^T (A p); alpha = rr/<p,q>; z += alpha p; r -= alpha q; beta; p = r + beta p.
-void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last) {
+void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, int start) {
+    if (start) {
+        // first iteration of an ADMM step on the folded path: the products run
+        // whatever the CG start test says (a step without CG iterations is
+        // rare) and the update evaluates the test from the right-hand side's
+        // partials, so no launch separates the right-hand side from A p
+        apply(0, YT, XP, -1, 1.0, G_ADMM);
+        ConvLaunch c = ca[0];
+        c.fold = 2;
+        c.fr = XR;
+        c.fp = XP;
+        c.fit = it;
+        c.part = T.cpart;
+        conv(c, 1, XQ, YT, XP, 1.0, G_ADMM);
+        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
+                         CgStart{st.cg_tol, st.cg_rate, st.cg_floor, 1});
+        return;
+    }
     apply(0, YT, XP, -1, 1.0, gate);
     if (folded_cg()) {
         // q = p + A^T (A p) with the dot partials and the iteration mark formed
@@ -748,22 +766,25 @@ void Engine::admm_step() {
     // w_y = u_y + v_s was written by the previous step's projection (or refresh)
     if (folded_cg()) {
         // h = u_x - A^T w_y formed in the launch's epilogue, which writes
-        // r = h - K z and p = r (not h) and the CG start partials
+        // r = h - K z and p = r (not h) and the CG start partials; the first
+        // CG update takes the start test
         ConvLaunch c = ca[0];
         c.fold = 1;
         c.fr = XR;
         c.fp = XP;
         c.fq = XK;
-        c.part = T.cpart;
+        c.part = T.spart;
         conv(c, 1, XH, YW, XU, -1.0, G_ADMM);
-        launch_cg_start_folded(T, st.cg_tol, st.cg_rate, st.cg_floor, st.cg_max_iters, G_ADMM, stream);
+        const int nl = std::max(1, cg_launch);
+        for (int i = 0; i < nl; ++i)
+            cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == nl - 1, i == 0);
     } else {
         apply(1, XH, YW, XU, -1.0, G_ADMM);                      // h = u_x - A^T w_y
         launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
                        st.cg_max_iters, G_ADMM, stream);         // r = h - K z
+        for (int i = 0; i < cg_launch; ++i)
+            cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == cg_launch - 1);
     }
-    for (int i = 0; i < cg_launch; ++i)
-        cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == cg_launch - 1);
     launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; u~_tau, tau, kappa
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update

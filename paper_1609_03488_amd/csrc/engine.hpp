@@ -217,8 +217,10 @@ class Engine {
     // ---- device work (enqueue only)
     void apply(int adj, int out, int in, int base, double sigma, int gate);
     void conv(const ConvLaunch& c, int adj, int out, int in, int base, double sigma, int gate);
-    // last = 1: the step's last CG launch (records a step that needed more)
-    void cg_iter(int z, int gate, int cg_max, int track, int it, int last = 0);
+    // last = 1: the step's last CG launch (records a step that needed more);
+    // start = 1: the first iteration of a step on the folded path (ungated
+    // products, the update takes the CG start test)
+    void cg_iter(int z, int gate, int cg_max, int track, int it, int last = 0, int start = 0);
     // CG steps run folded into the A^T launch (FFT engine chosen and the tables allow it)
     bool folded_cg() const { return fold_cg && prec == 1 && st.conv_mfma == 2 && !ca.empty() && ca[0].fft; }
     void admm_step();

@@ -207,22 +207,42 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, int p, int q, int it,
                                                       int cg_max, int gate, int track, int folded,
-                                                      int last) {
-    __shared__ double sh[4 * (VEC_NT / 64)];
+                                                      int last, CgStart cs) {
+    __shared__ double sh[12 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, gate) || sc[SC_CGRUN] != (double)it) return;
+    const bool rec = !xt.is_y && xt.index == d.xt0 && threadIdx.x == 0;
     double s[4];
-    if (folded) inst_csum4(tb, d, s, sh);   // partials of the A^T launch
-    else inst_xsum4(tb, d, s, sh);          // partials of k_cg_dot
+    double h0 = 0.0, h1 = 0.0;
+    if (folded) inst_csum4(tb, d, s, cs.on != 0, h0, h1, sh);   // partials of the A^T launch(es)
+    else inst_xsum4(tb, d, s, sh);                              // partials of k_cg_dot
+    double tol;
+    if (cs.on) {
+        // the step's CG start test, from the right-hand side launch's partials
+        // ||r||^2, ||h||^2 (the products of this first iteration ran whatever
+        // its outcome); every workgroup evaluates it
+        tol = cg_tolerance(sc[SC_ITER], h1, cs.zeta, cs.rate, cs.floor_);
+        const bool act = cg_max > 0 && sqrt(h0) > tol && std::isfinite(h0);
+        if (rec) {
+            sc[SC_RR] = h0;
+            sc[SC_HN] = sqrt(h1);
+            sc[SC_CGTOL] = tol;
+            sc[SC_CGIT] = 0.0;
+            sc[SC_CGACT] = act ? 1.0 : 0.0;
+        }
+        if (!act) return;
+    } else {
+        tol = sc[SC_CGTOL];
+    }
     const double pq = s[0], rr = s[1], rq = s[2], qq = s[3];
     const double al = rr / pq;
     const bool ok = pq > 0.0 && std::isfinite(al);
     const double rr1 = fma(al * al, qq, fma(-2.0 * al, rq, rr));
     const double be = rr > 0.0 ? rr1 / rr : 0.0;
-    const bool more = ok && std::isfinite(rr1) && sqrt(rr1) > sc[SC_CGTOL] && it + 1 < cg_max;
-    if (!xt.is_y && xt.index == d.xt0 && threadIdx.x == 0) {
+    const bool more = ok && std::isfinite(rr1) && sqrt(rr1) > tol && it + 1 < cg_max;
+    if (rec) {
         sc[SC_PQ] = pq;
         sc[SC_ALPHA] = ok ? al : 0.0;
         sc[SC_RR] = ok ? rr1 : rr;
@@ -480,12 +500,7 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
     const bool use_x = true;
     const bool use_y = mode == FIN_RESID || mode == FIN_NORMS || mode == FIN_ETA;
     const int nslot = (mode == FIN_RESID) ? 3 : (mode == FIN_CG_INIT ? 2 : 1);
-    if (mode == FIN_CG_INIT && fa.i1) {
-        // CG start folded into the right-hand side's A^T launch: its transform
-        // workgroups' partials, then its initialisation workgroups'
-        x0 = sum_parts<VEC_NT>(tb.cpart, d.cp0, d.cp1, 0, sh) + sum_parts<VEC_NT>(tb.cpart, d.ip0, d.ip1, 0, sh);
-        x1 = sum_parts<VEC_NT>(tb.cpart, d.cp0, d.cp1, 1, sh) + sum_parts<VEC_NT>(tb.cpart, d.ip0, d.ip1, 1, sh);
-    } else if (use_x) {
+    if (use_x) {
         x0 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 0, sh);
         if (nslot > 1) x1 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 1, sh);
         if (nslot > 2) x2 = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, 2, sh);
@@ -498,16 +513,11 @@ __global__ __launch_bounds__(VEC_NT) void k_finalize(Tables tb, int mode, int ga
     if (threadIdx.x != 0) return;
     switch (mode) {
         case FIN_CG_INIT: {
-            // tol = ||h|| max(floor, zeta / (k+1)^rate) at ADMM step k (k = 0 in setup)
-            const double zeta = fa.a0, rate = fa.a1, floor_ = fa.a2;
             const int cg_max = fa.i0;
-            const double hn = sqrt(x1);
             const double k = (gate == G_SETUP || gate == G_SETUP_CG) ? 0.0 : sc[SC_ITER];
-            double rel = zeta > 0.0 ? zeta / pow(k + 1.0, rate) : 0.0;
-            rel = rel > floor_ ? rel : floor_;
-            const double tol = hn * rel;
+            const double tol = cg_tolerance(k, x1, fa.a0, fa.a1, fa.a2);
             sc[SC_RR] = x0;
-            sc[SC_HN] = hn;
+            sc[SC_HN] = sqrt(x1);
             sc[SC_CGTOL] = tol;
             sc[SC_CGIT] = 0.0;
             sc[SC_CGRUN] = -1.0;
@@ -811,19 +821,15 @@ void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h
                  floor_, cg_max, gate);
     k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_INIT, gate, FinArgs{zeta, rate, floor_, cg_max, 0});
 }
-void launch_cg_start_folded(const Tables& t, double zeta, double rate, double floor_, int cg_max, int gate,
-                            hipStream_t st) {
-    k_finalize<<<t.ninst, VEC_NT, 0, st>>>(t, FIN_CG_INIT, gate, FinArgs{zeta, rate, floor_, cg_max, 1});
-}
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_cg_dot, t.nx_tiles, VEC_NT, st, t, p, q, r, it, gate);
 }
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
-                      int gate, int track, hipStream_t st, int folded, int last) {
+                      int gate, int track, hipStream_t st, int folded, int last, CgStart cs) {
     // the update's own gate is the phase test of the CG gate plus the mark of k_cg_dot
     const int g = gate == G_ADMM_CG ? G_ADMM : gate == G_SETUP_CG ? G_SETUP : G_ALL;
     CGS_DISPATCH(prec, k_cg_update, t.nx_tiles + (track ? t.ny_tiles : 0), VEC_NT, st, t, z, r, p, q,
-                 it, cg_max, g, track, folded, last);
+                 it, cg_max, g, track, folded, last, cs);
 }
 void launch_snapshot(int prec, const Tables& t, int restore, hipStream_t st) {
     CGS_DISPATCH(prec, k_snapshot, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, restore);

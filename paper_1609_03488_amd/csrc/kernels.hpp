@@ -71,10 +71,6 @@ void launch_gemv(int prec, const Tables& t, const DenseLaunch& d, int adj, int o
 //       tol = ||h|| * max(floor, zeta / (k+1)^rate), CG active iff ||r|| > tol.
 void launch_cg_init(int prec, const Tables& t, int z, int r, int p, int q, int h, int have_q,
                     double zeta, double rate, double floor, int cg_max, int gate, hipStream_t st);
-// the CG start when the right-hand side's A^T launch formed r, p and the
-// partials (ConvLaunch::fold = 1): tolerance and start flag only
-void launch_cg_start_folded(const Tables& t, double zeta, double rate, double floor_, int cg_max, int gate,
-                            hipStream_t st);
 // partials of <p, q>, ||r||^2, <r, q>, ||q||^2; marks iteration `it` as in progress
 void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int gate, hipStream_t st);
 // alpha = ||r||^2 / <p, q>; z += alpha p; r -= alpha q; beta = ||r'||^2 / ||r||^2
@@ -82,8 +78,16 @@ void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int g
 // p = r' + beta p while CG goes on.
 // track = 1: also K z += alpha q and A z += alpha (A p) (carried products)
 // `it`: CG iteration of the current loop (must match the preceding launch_cg_dot)
+// The CG start test evaluated by the first update of a step (folded path: the
+// right-hand side's partials are in Tables::spart and the first iteration's
+// products ran ungated)
+struct CgStart {
+    double zeta, rate, floor_;
+    int on;
+};
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
-                      int gate, int track, hipStream_t st, int folded = 0, int last = 0);
+                      int gate, int track, hipStream_t st, int folded = 0, int last = 0,
+                      CgStart cs = CgStart{0.0, 0.0, 0.0, 0});
 // (folded = 1: the partials come from the A^T launch of ConvLaunch::fold = 2;
 // last = 1: the step's last CG launch of a round run from a snapshot; when CG
 // would go on the instance is suspended, phase 3, for the host to run the
