@@ -736,7 +736,7 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         c.part = T.cpart;
         conv(c, 1, XQ, YT, XP, 1.0, G_ADMM);
         launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
-                         CgStart{st.cg_tol, st.cg_rate, st.cg_floor, 1});
+                         CgStart{st.cg_tol, st.cg_rate, st.cg_floor, 1, 1});
         return;
     }
     apply(0, YT, XP, -1, 1.0, gate);
@@ -750,7 +750,9 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         c.fit = it;
         c.part = T.cpart;
         conv(c, 1, XQ, YT, XP, 1.0, gate);
-        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last);
+        // (on the ADMM path the update that ends CG also takes the tau products)
+        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
+                         CgStart{0.0, 0.0, 0.0, 0, gate == G_ADMM_CG && track ? 1 : 0});
         return;
     }
     apply(1, XQ, YT, XP, 1.0, gate);
@@ -785,7 +787,8 @@ void Engine::admm_step() {
         for (int i = 0; i < cg_launch; ++i)
             cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == cg_launch - 1);
     }
-    launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; u~_tau, tau, kappa
+    if (!folded_cg())                                            // (else in the last CG update)
+        launch_tau_dots(prec, T, st.alpha, 1, stream);           // z_y = w_y + A z; c^T z_x + b^T z_y
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
 }

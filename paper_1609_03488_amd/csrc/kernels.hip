@@ -195,6 +195,33 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
     }
 }
 
+// The scalar products of u~_tau for one tile (Section V-B: the tau component
+// of the subspace projection): c^T z_x over an X tile, or z_y = w_y + A z
+// (the carried product) stored and b^T z_y over a Y tile; FP64 partial in
+// slot 0 of the tile's X or Y partials.
+template <typename T>
+DEVI void tau_tile(const Tables& tb, const InstDesc& d, const XYTile& xt, double* sh) {
+    gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
+    double s0 = 0.0;
+    if (xt.is_y) {
+        gptr<const T> wy = yvec<T>(d, YW);
+        gptr<const T> az = yvec<T>(d, YA);
+        gptr<T> zy = yvec<T>(d, YZ);
+        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT) {
+            const T v = (T)((double)wy[i] + (double)az[i]);
+            zy[i] = v;
+            s0 = fma((double)a[i], (double)v, s0);
+        }
+    } else {
+        gptr<const T> zx = xvec<T>(d, XZ);
+        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
+            s0 = fma((double)a[i], (double)zx[i], s0);
+    }
+    s0 = block_sum<VEC_NT>(s0, sh);
+    double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
+    if (threadIdx.x == 0) part[0] = s0;
+}
+
 // One CG step after the products: alpha = ||r||^2 / <p, q>; z += alpha p;
 // r' = r - alpha q (and the carried K z, A z when tracking); then the next
 // direction p = r' + beta p in the same pass.  beta needs ||r'||^2 before r'
@@ -232,7 +259,10 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
             sc[SC_CGIT] = 0.0;
             sc[SC_CGACT] = act ? 1.0 : 0.0;
         }
-        if (!act) return;
+        if (!act) {
+            if (cs.tau) tau_tile<T>(tb, d, xt, sh);
+            return;
+        }
     } else {
         tol = sc[SC_CGTOL];
     }
@@ -260,27 +290,52 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
         if (last && more) sc[SC_PHASE] = 3.0;
         sc[SC_CGACT] = more ? 1.0 : 0.0;
     }
-    if (!ok) return;
+    // the step's last CG update also does the work of k_tau_dots on the final
+    // z and A z (cs.tau: every instance's CG ends in an update of this loop)
+    const bool tw = cs.tau && !more;
+    if (!ok) {
+        if (tw) tau_tile<T>(tb, d, xt, sh);
+        return;
+    }
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
+    double s0 = 0.0;
     if (!xt.is_y) {
         gptr<T> zv = xvec<T>(d, z);
         gptr<T> rv = xvec<T>(d, r);
         gptr<T> pv = xvec<T>(d, p);
         gptr<const T> qv = xvec<T>(d, q);
         gptr<T> kz = xvec<T>(d, XK);
+        gptr<const T> cv = xvec<T>(d, XC);
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             const double qi = (double)qv[i], pi = (double)pv[i];
-            zv[i] = (T)fma(al, pi, (double)zv[i]);
+            const T zi = (T)fma(al, pi, (double)zv[i]);
+            zv[i] = zi;
             const T ri = (T)fma(-al, qi, (double)rv[i]);
             rv[i] = ri;
             if (track) kz[i] = (T)fma(al, qi, (double)kz[i]);
             if (more) pv[i] = (T)fma(be, pi, (double)ri);
+            if (tw) s0 = fma((double)cv[i], (double)zi, s0);
         }
     } else {
         gptr<T> az = yvec<T>(d, YA);
         gptr<const T> ap = yvec<T>(d, YT);
-        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT)
-            az[i] = (T)fma(al, (double)ap[i], (double)az[i]);
+        gptr<const T> wy = yvec<T>(d, YW);
+        gptr<const T> bv = yvec<T>(d, YB);
+        gptr<T> zy = yvec<T>(d, YZ);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
+            const T ai = (T)fma(al, (double)ap[i], (double)az[i]);
+            az[i] = ai;
+            if (tw) {
+                const T v = (T)((double)wy[i] + (double)ai);
+                zy[i] = v;
+                s0 = fma((double)bv[i], (double)v, s0);
+            }
+        }
+    }
+    if (tw) {
+        s0 = block_sum<VEC_NT>(s0, sh);
+        double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
+        if (threadIdx.x == 0) part[0] = s0;
     }
 }
 
@@ -306,18 +361,14 @@ __global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha, in
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
+    if (form_zy) {
+        tau_tile<T>(tb, d, xt, sh);
+        return;
+    }
     gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
     gptr<T> b = xt.is_y ? yvec<T>(d, YZ) : xvec<T>(d, XZ);
     double s0 = 0.0;
-    if (xt.is_y && form_zy) {
-        gptr<const T> wy = yvec<T>(d, YW);
-        gptr<const T> az = yvec<T>(d, YA);
-        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT) {
-            const T zy = (T)((double)wy[i] + (double)az[i]);
-            b[i] = zy;
-            s0 = fma((double)a[i], (double)zy, s0);
-        }
-    } else {
+    {
         for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
             s0 = fma((double)a[i], (double)b[i], s0);
     }

@@ -84,10 +84,14 @@ void launch_cg_dot(int prec, const Tables& t, int p, int q, int r, int it, int g
 struct CgStart {
     double zeta, rate, floor_;
     int on;
+    // 1: the update in which an instance's CG ends also does the work of
+    // launch_tau_dots (form_zy = 1) on the final z and A z (folded ADMM path,
+    // where some update of the loop always runs)
+    int tau;
 };
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
                       int gate, int track, hipStream_t st, int folded = 0, int last = 0,
-                      CgStart cs = CgStart{0.0, 0.0, 0.0, 0});
+                      CgStart cs = CgStart{0.0, 0.0, 0.0, 0, 0});
 // (folded = 1: the partials come from the A^T launch of ConvLaunch::fold = 2;
 // last = 1: the step's last CG launch of a round run from a snapshot; when CG
 // would go on the instance is suspended, phase 3, for the host to run the
