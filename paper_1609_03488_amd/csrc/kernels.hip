@@ -306,14 +306,17 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
         gptr<const T> qv = xvec<T>(d, q);
         gptr<T> kz = xvec<T>(d, XK);
         gptr<const T> cv = xvec<T>(d, XC);
+        // (once CG has ended, r is dead: the next solve forms it afresh)
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             const double qi = (double)qv[i], pi = (double)pv[i];
             const T zi = (T)fma(al, pi, (double)zv[i]);
             zv[i] = zi;
-            const T ri = (T)fma(-al, qi, (double)rv[i]);
-            rv[i] = ri;
+            if (more) {
+                const T ri = (T)fma(-al, qi, (double)rv[i]);
+                rv[i] = ri;
+                pv[i] = (T)fma(be, pi, (double)ri);
+            }
             if (track) kz[i] = (T)fma(al, qi, (double)kz[i]);
-            if (more) pv[i] = (T)fma(be, pi, (double)ri);
             if (tw) s0 = fma((double)cv[i], (double)zi, s0);
         }
     } else {
