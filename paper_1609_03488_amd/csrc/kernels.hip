@@ -385,6 +385,36 @@ __global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha, in
 // it for the projection.  Tiles of a second-order cone then store the cone's
 // head value (u_bar - v at its first row) and partial sums of squares of the
 // tail (Y partial slot 1).
+// A thread's elements of a Y tile of u_y, z_y, g_y, v_s, loaded at once
+// (ahead of a reduction, and ahead of stores into the same vectors, which
+// element by element would order each load after the previous stores);
+// pv() is ybar_minus_v on them.
+template <typename T>
+struct YbarTile {
+    static constexpr int R = VEC_TILE / VEC_NT;
+    T u[R], z[R], g[R], v[R];
+    DEVI void load(const InstDesc& d, const VecTile& tl) {
+        gptr<const T> pu = yvec<T>(d, YU), pz = yvec<T>(d, YZ), pg = yvec<T>(d, YG), pvv = yvec<T>(d, YV);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t o = threadIdx.x + (int64_t)j * VEC_NT;
+            const int64_t i = tl.start + (o < tl.len ? o : 0);
+            u[j] = pu[i];
+            z[j] = pz[i];
+            g[j] = pg[i];
+            v[j] = pvv[i];
+        }
+    }
+    DEVI bool has(const VecTile& tl, int j) const { return threadIdx.x + (int64_t)j * VEC_NT < tl.len; }
+    DEVI int64_t at(const VecTile& tl, int j) const { return tl.start + threadIdx.x + (int64_t)j * VEC_NT; }
+    DEVI double pv(int j, double ut, double alpha) const {
+        const double uy = (double)u[j];
+        const double ut_y = (double)z[j] - ut * (double)g[j];
+        const double ub = alpha * ut_y + (1.0 - alpha) * uy;
+        return ub - (double)v[j];
+    }
+};
+
 template <typename T>
 __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
     __shared__ double sh[VEC_NT / 64];
@@ -392,6 +422,8 @@ __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
     const InstDesc d = tb.inst[tl.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
+    YbarTile<T> yb;
+    if (tl.seg >= 0) yb.load(d, tl);   // (in flight during the sums)
     const double x0 = inst_xsum(tb, d, 0, sh);
     const double y0 = inst_ysum(tb, d, 0, sh);
     const double ut = (sc[SC_TAU] + sc[SC_KAPPA] + x0 + y0) / sc[SC_ETA];
@@ -399,10 +431,11 @@ __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
     if (tl.seg < 0) return;
     const SocSeg sg = tb.seg[tl.seg];
     double s0 = 0.0;
-    for (int64_t i = tl.start + threadIdx.x; i < tl.start + tl.len; i += VEC_NT) {
-        double ub;
-        const double pv = ybar_minus_v<T>(d, i, ut, alpha, ub);
-        if (i == sg.start) tb.seg_val[2 * tl.seg] = pv;
+#pragma unroll
+    for (int j = 0; j < YbarTile<T>::R; ++j) {
+        if (!yb.has(tl, j)) continue;
+        const double pv = yb.pv(j, ut, alpha);
+        if (yb.at(tl, j) == sg.start) tb.seg_val[2 * tl.seg] = pv;
         else s0 = fma(pv, pv, s0);
     }
     s0 = block_sum<VEC_NT>(s0, sh);
@@ -426,24 +459,40 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         sc[SC_TAU] = tnew;
         sc[SC_ITER] += 1.0;
     }
-    const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     if (!xt.is_y) {
         gptr<T> ux = xvec<T>(d, XU);
         gptr<const T> zx = xvec<T>(d, XZ);
         gptr<const T> gx = xvec<T>(d, XG);
-        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            const double utx = (double)zx[i] - ut * (double)gx[i];
-            ux[i] = (T)(alpha * utx + (1.0 - alpha) * (double)ux[i]);
+        constexpr int R = VEC_TILE / VEC_NT;
+        T zl[R], gl[R], ul[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {   // every load before the first store
+            const int64_t o = threadIdx.x + (int64_t)j * VEC_NT;
+            const int64_t i = xt.t.start + (o < xt.t.len ? o : 0);
+            zl[j] = zx[i];
+            gl[j] = gx[i];
+            ul[j] = ux[i];
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t o = threadIdx.x + (int64_t)j * VEC_NT;
+            if (o >= xt.t.len) continue;
+            const double utx = (double)zl[j] - ut * (double)gl[j];
+            ux[xt.t.start + o] = (T)(alpha * utx + (1.0 - alpha) * (double)ul[j]);
         }
         return;
     }
     gptr<T> uy = yvec<T>(d, YU);
     gptr<T> vs = yvec<T>(d, YV);
     gptr<T> wy = yvec<T>(d, YW);
+    YbarTile<T> yb;
+    yb.load(d, xt.t);
     if (xt.t.seg < 0) {
-        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            double ub;
-            const double pv = ybar_minus_v<T>(d, i, ut, alpha, ub);
+#pragma unroll
+        for (int j = 0; j < YbarTile<T>::R; ++j) {
+            if (!yb.has(xt.t, j)) continue;
+            const int64_t i = yb.at(xt.t, j);
+            const double pv = yb.pv(j, ut, alpha);
             const double pr = pv > 0.0 ? pv : 0.0;
             const T u = (T)pr, v = (T)(pr - pv);
             uy[i] = u;
@@ -464,9 +513,11 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         mode = 2;
         a = 0.5 * (t + nz);
     }
-    for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-        double ub;
-        const double pv = ybar_minus_v<T>(d, i, ut, alpha, ub);
+#pragma unroll
+    for (int j = 0; j < YbarTile<T>::R; ++j) {
+        if (!yb.has(xt.t, j)) continue;
+        const int64_t i = yb.at(xt.t, j);
+        const double pv = yb.pv(j, ut, alpha);
         double pr;
         if (mode == 0) pr = pv;
         else if (mode == 1) pr = 0.0;
