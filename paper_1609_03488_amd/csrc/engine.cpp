@@ -495,8 +495,9 @@ void Engine::drop_graph() {
 }
 
 // CG launches per step for the next check interval: the most CG iterations any
-// running instance used in a step of the last interval, within [1,
-// cg_max_iters]; fixed at cg_max_iters when adaptation is off.  An interval
+// running instance used in a step of the last interval (cg_max_iters for an
+// instance's first interval), within [1, cg_max_iters]; fixed at cg_max_iters
+// when adaptation is off.  An interval
 // whose steps needed more is run again from its snapshot (Engine::rollback).
 void Engine::adapt_cg() {
     if (!st.cg_adaptive) {
@@ -506,7 +507,10 @@ void Engine::adapt_cg() {
     double need = 0.0;
     for (int i = 0; i < T.ninst; ++i) {
         const double* sc = scalars(i);
-        if (sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0) need = std::max(need, sc[SC_CGMAXLAST]);
+        if (sc[SC_ACTIVE] == 0.0 || sc[SC_PHASE] != 1.0) continue;
+        // an instance's first interval has nothing to predict from (and its
+        // cold-started CG solves take the most iterations of the solve)
+        need = std::max(need, sc[SC_ITER] == 0.0 ? (double)st.cg_max_iters : sc[SC_CGMAXLAST]);
     }
     cg_launch = std::max(1, std::min(st.cg_max_iters, (int)need));
 }
