@@ -459,40 +459,24 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         sc[SC_TAU] = tnew;
         sc[SC_ITER] += 1.0;
     }
+    const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     if (!xt.is_y) {
         gptr<T> ux = xvec<T>(d, XU);
         gptr<const T> zx = xvec<T>(d, XZ);
         gptr<const T> gx = xvec<T>(d, XG);
-        constexpr int R = VEC_TILE / VEC_NT;
-        T zl[R], gl[R], ul[R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {   // every load before the first store
-            const int64_t o = threadIdx.x + (int64_t)j * VEC_NT;
-            const int64_t i = xt.t.start + (o < xt.t.len ? o : 0);
-            zl[j] = zx[i];
-            gl[j] = gx[i];
-            ul[j] = ux[i];
-        }
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int64_t o = threadIdx.x + (int64_t)j * VEC_NT;
-            if (o >= xt.t.len) continue;
-            const double utx = (double)zl[j] - ut * (double)gl[j];
-            ux[xt.t.start + o] = (T)(alpha * utx + (1.0 - alpha) * (double)ul[j]);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
+            const double utx = (double)zx[i] - ut * (double)gx[i];
+            ux[i] = (T)(alpha * utx + (1.0 - alpha) * (double)ux[i]);
         }
         return;
     }
     gptr<T> uy = yvec<T>(d, YU);
     gptr<T> vs = yvec<T>(d, YV);
     gptr<T> wy = yvec<T>(d, YW);
-    YbarTile<T> yb;
-    yb.load(d, xt.t);
     if (xt.t.seg < 0) {
-#pragma unroll
-        for (int j = 0; j < YbarTile<T>::R; ++j) {
-            if (!yb.has(xt.t, j)) continue;
-            const int64_t i = yb.at(xt.t, j);
-            const double pv = yb.pv(j, ut, alpha);
+        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
+            double ub;
+            const double pv = ybar_minus_v<T>(d, i, ut, alpha, ub);
             const double pr = pv > 0.0 ? pv : 0.0;
             const T u = (T)pr, v = (T)(pr - pv);
             uy[i] = u;
@@ -501,6 +485,8 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         }
         return;
     }
+    YbarTile<T> yb;
+    yb.load(d, xt.t);   // (in flight during the cone's norm sum)
     const SocSeg sg = tb.seg[xt.t.seg];
     const double t = tb.seg_val[2 * xt.t.seg];
     const double nz = sqrt(sum_parts_all<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 1, sh));
