@@ -167,9 +167,9 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
     }
     const ConvTile tl = cl.ftiles[blockIdx.x];
     const InstDesc d = tb.inst[tl.inst];
+    const ConvBlock cb = cl.blocks[tl.blk];   // (loaded beside the instance, ahead of the gate)
     if (!gate_ok(scal(d), gate)) return;
     if (FOLD == 2 && (int)blockIdx.x == d.cp0 && threadIdx.x == 0) scal(d)[SC_CGRUN] = (double)cl.fit;
-    const ConvBlock cb = cl.blocks[tl.blk];
     int64_t n_out, n_in, off;
     gptr<float> o;
     gptr<const float> src;

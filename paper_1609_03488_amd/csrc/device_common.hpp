@@ -29,15 +29,19 @@ DEVI gptr<double> scal(const InstDesc& d) { return (gptr<double>)d.base; }
 DEVI int* counters(const InstDesc& d) { return reinterpret_cast<int*>(d.base + NSC * 8); }
 
 DEVI bool gate_ok(gptr<const double> sc, int gate) {
+    // the three flags are loaded together (short-circuit tests would issue
+    // each load only after the previous one returned)
+    const double act = sc[SC_ACTIVE], ph = sc[SC_PHASE], cg = sc[SC_CGACT];
+    const bool on = act != 0.0;
     switch (gate) {
         case G_ALL: return true;
-        case G_SETUP: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0;
-        case G_SETUP_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 0.0 && sc[SC_CGACT] != 0.0;
+        case G_SETUP: return on & (ph == 0.0);
+        case G_SETUP_CG: return on & (ph == 0.0) & (cg != 0.0);
         case G_ADMM:
-        case G_CHECK: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0;
-        case G_ADMM_CG: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 1.0 && sc[SC_CGACT] != 0.0;
-        case G_ANY_CG: return sc[SC_CGACT] != 0.0;
-        case G_CHECK_ANY: return sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] >= 1.0;
+        case G_CHECK: return on & (ph == 1.0);
+        case G_ADMM_CG: return on & (ph == 1.0) & (cg != 0.0);
+        case G_ANY_CG: return cg != 0.0;
+        case G_CHECK_ANY: return on & (ph >= 1.0);
         default: return false;
     }
 }
