@@ -104,7 +104,8 @@ typedef struct {
     int32_t cg_adaptive;   /* 1 (default): a check interval runs as many CG launches
                               per step as the most CG iterations any instance used in
                               a step of the previous interval (at least 1, at most
-                              cg_max_iters), starting from a copy of the state each
+                              cg_max_iters; cg_max_iters in an instance's first
+                              interval), starting from a copy of the state each
                               step hands to the next.  When some step's CG would have
                               gone on after its last launch, the interval is restored
                               from that copy and run again with 2 L + 1 launches
