@@ -500,7 +500,8 @@ void Engine::drop_graph() {
 // when adaptation is off.  An interval
 // whose steps needed more is run again from its snapshot (Engine::rollback).
 void Engine::adapt_cg() {
-    if (!st.cg_adaptive) {
+    if (!st.cg_adaptive || !snap_ok) {
+        // (without a copy to run an interval again from, no prediction)
         cg_launch = st.cg_max_iters;
         return;
     }
