@@ -72,8 +72,10 @@ enum {
     CGS_FP64 = 0,   /* everything in FP64                                        */
     CGS_FP32 = 1,   /* FP32 vectors and operator applies, FP64 scalars/norms     */
     CGS_BF16 = 2    /* CGS_FP32 plus BF16 MFMA products (FP32 accumulation) for a
-                       dense block shared by a batch; residual checks and the
-                       final iterations use the FP32 operator                    */
+                       dense block shared by a batch: two phases on the BF16
+                       matrix (8, then ~16 significant bits), then the residual
+                       test -- and, where it fails, further iterations -- on the
+                       FP32 operator (see bf16_phase1_digits)                    */
 };
 
 /* Block kinds of an operator description. */
@@ -100,7 +102,11 @@ typedef struct {
     int32_t bf16_phase1_digits; /* CGS_BF16: the BF16-product phase solves to
                               max(eps, 10^-digits); the refinement phase (BF16 hi/lo
                               products, ~16 significant bits) then continues from its
-                              state to eps with a fresh setup solve (default 3)       */
+                              state to eps / 2 with a fresh setup solve; the last
+                              phase tests the point on the FP32 operator (dense
+                              products from the FP32 copy of the blocks) and, for an
+                              instance that fails the test, iterates on that operator
+                              with its own setup solve until it passes (default 3)  */
     int32_t cg_adaptive;   /* 1 (default): a check interval runs as many CG launches
                               per step as the most CG iterations any instance used in
                               a step of the previous interval (at least 1, at most
@@ -164,6 +170,11 @@ typedef struct {
     double tau, kappa;     /* embedding scalars at exit                               */
     double setup_s;        /* wall time of the setup (embedding vector) phase         */
     double solve_s;        /* wall time of the iterations                             */
+    int32_t cert_precision; /* arithmetic of the operator whose residual test gave
+                              status: the solver's precision, or CGS_FP32 for a
+                              CGS_BF16 instance the FP32 phase tested (CGS_BF16 if
+                              an earlier phase ended it without a solution)        */
+    int32_t reserved_;
 } cgs_info;
 
 /* ---------------------------------------------------------------- errors */
@@ -236,7 +247,8 @@ int cgs_solver_reset(cgs_solver* s, int64_t inst);
 /* Solve every instance from its current state (fresh: u = v = (0, 0, 1)).
  * info: array of `batch` entries (may be NULL).  With CGS_BF16 and dense
  * blocks, the dense applies of all instances run as one BF16 MFMA GEMM
- * (FP32 accumulation); the solve has two phases (see bf16_phase1_digits). */
+ * (FP32 accumulation); the solve has three phases (see bf16_phase1_digits),
+ * the last on the FP32 operator. */
 int cgs_solve(cgs_solver* s, cgs_info* info);
 /* Run exactly `iters` ADMM steps on every unfinished instance, with no
  * termination test (the setup solve runs first if needed). */

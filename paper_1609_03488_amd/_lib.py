@@ -52,6 +52,7 @@ class Info(C.Structure):
         ("pobj", C.c_double), ("dobj", C.c_double), ("res_pri", C.c_double),
         ("res_dual", C.c_double), ("gap", C.c_double), ("tau", C.c_double),
         ("kappa", C.c_double), ("setup_s", C.c_double), ("solve_s", C.c_double),
+        ("cert_precision", C.c_int32), ("reserved_", C.c_int32),
     ]
 
     def as_dict(self) -> dict:

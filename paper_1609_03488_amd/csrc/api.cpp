@@ -92,6 +92,9 @@ struct cgs_solver {
     cgs::Scaling scl;
     int64_t n = 0, m = 0, batch = 0;
     std::vector<char> has_data;
+    // CGS_BF16 batches: arithmetic of the operator whose residual test gave
+    // each instance's outcome in the last solve
+    std::vector<int> cert;
 };
 
 struct ServerReq {
@@ -348,6 +351,7 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
     s->m = op->m;
     s->batch = batch;
     s->has_data.assign((size_t)batch, 0);
+    s->cert.assign((size_t)batch, st->precision);
     *out = s.release();
     return CGS_OK;
 }
@@ -510,11 +514,19 @@ int cgs_solve(cgs_solver* s, cgs_info* info) {
     if (e.use_gemm) {
         // Phase 1: BF16 products, to max(eps, 10^-digits).  Phase 2: the
         // refinement operator (hi/lo products) from phase 1's state, with the
-        // embedding vector recomputed for that operator, to eps.
+        // embedding vector recomputed for that operator, to eps * kPhase2Margin.
+        // Phase 3: the FP32 operator (dense products on the vector ALU from the
+        // FP32 copy of the blocks): the residual test runs on it at phase 2's
+        // point, and an instance that fails it iterates on that operator (with
+        // its own embedding vector) until it passes.  The reported status is
+        // always that of the FP32 operator's test (cgs_info.cert_precision).
+        constexpr double kPhase2Margin = 0.5;
         const double eps = e.st.eps;
         const double eps1 = std::max(eps, std::pow(10.0, -(double)e.st.bf16_phase1_digits));
+        const double eps2 = eps * kPhase2Margin;
+        std::fill(s->cert.begin(), s->cert.end(), CGS_BF16);
         e.gemm_corr = 0;
-        e.st.eps = eps1;
+        e.st.eps = std::max(eps1, eps2);
         e.drop_graph();
         CGS_TRY(run_setup_if_needed(s, nullptr));
         e.refresh();
@@ -522,22 +534,56 @@ int cgs_solve(cgs_solver* s, cgs_info* info) {
         int rc = solve_rounds(s);
         e.st.eps = eps;
         if (rc != CGS_OK) return rc;
-        if (eps1 > eps) {
+        auto reopen = [&](double phase) -> int {
+            // instances the last phase solved run again (the others keep their outcome)
             CGS_TRY(e.fetch_scalars());
+            int n = 0;
             for (int i = 0; i < e.T.ninst; ++i) {
-                const double* sc = e.scalars(i);
-                if (sc[cgs::SC_STATUS] == (double)CGS_SOLVED) {
-                    CGS_TRY(e.set_scalar(i, cgs::SC_STATUS, 0.0));
-                    CGS_TRY(e.set_scalar(i, cgs::SC_ACTIVE, 1.0));
-                    CGS_TRY(e.set_scalar(i, cgs::SC_PHASE, 0.0));
-                }
+                if (e.scalars(i)[cgs::SC_STATUS] != (double)CGS_SOLVED) continue;
+                CGS_TRY(e.set_scalar(i, cgs::SC_STATUS, 0.0));
+                CGS_TRY(e.set_scalar(i, cgs::SC_ACTIVE, 1.0));
+                CGS_TRY(e.set_scalar(i, cgs::SC_PHASE, phase));
+                ++n;
             }
+            return n;
+        };
+        if (eps1 > eps2) {
+            const int r = reopen(0.0);
+            if (r < 0) return r;
             e.gemm_corr = 1;
+            e.st.eps = eps2;
             e.drop_graph();
             CGS_TRY(run_setup_if_needed(s, nullptr));
             e.refresh();
-            CGS_TRY(solve_rounds(s));
+            rc = solve_rounds(s);
+            e.st.eps = eps;
+            if (rc != CGS_OK) return rc;
         }
+        // phase 3
+        const int nre = reopen(1.0);
+        if (nre < 0) return nre;
+        e.use_gemm = 0;
+        e.gemm_corr = 0;
+        e.drop_graph();
+        rc = CGS_OK;
+        if (nre > 0) {
+            e.check(cgs::G_CHECK_ANY);   // the test alone: no step, no carried products
+            rc = e.fetch_scalars();
+            for (int i = 0; rc == CGS_OK && i < e.T.ninst; ++i) {
+                const double* sc = e.scalars(i);
+                s->cert[(size_t)i] = CGS_FP32;
+                if (sc[cgs::SC_ACTIVE] != 0.0 && sc[cgs::SC_PHASE] == 1.0)
+                    rc = e.set_scalar(i, cgs::SC_PHASE, 0.0);   // iterate: setup for this operator
+            }
+            if (rc == CGS_OK) rc = run_setup_if_needed(s, nullptr);
+            if (rc == CGS_OK) {
+                e.refresh();
+                rc = solve_rounds(s);
+            }
+        }
+        e.use_gemm = 1;
+        e.drop_graph();
+        if (rc != CGS_OK) return rc;
     } else {
         CGS_TRY(run_setup_if_needed(s, nullptr));
         e.refresh();   // carried A z, (I + A^T A) z of the warm start
@@ -550,6 +596,7 @@ int cgs_solve(cgs_solver* s, cgs_info* info) {
             e.fill_info(i, &info[i]);
             info[i].setup_s = t1 - t0;
             info[i].solve_s = t2 - t1;
+            info[i].cert_precision = e.use_gemm ? s->cert[(size_t)i] : e.precision;
         }
     }
     return CGS_OK;

@@ -203,6 +203,10 @@ struct Tables {
     double* ypart;       // 4 per Y tile
     double* cpart;       // 4 per workgroup of the A^T convolution launch (folded CG products)
     double* spart;       // the same for the right-hand side's A^T launch (folded CG start)
+    // slot-major partials of the update that ends CG for the projection that
+    // follows (CgStart::cone): tpart[j * (nx_tiles + ny_tiles) + b] for the
+    // workgroup b of an X-then-Y tile launch, slots 0 (tau products) to 3
+    double* tpart;
     int nx_tiles, ny_tiles, nseg, ninst;
 };
 

@@ -66,6 +66,12 @@ DEVI void dft8(cf* v) {
     v[3] = cadd(e[3], w3);
     v[7] = csub(e[3], w3);
 }
+// The transform's LDS array is padded by one entry per 32: the radix-8
+// stores of a stage hit addresses 8 or 64 entries apart across the lanes of a
+// wave, which without padding fall into the same few LDS banks.
+constexpr int LDS_L = FFT_L + FFT_L / 32;
+DEVI int lp(int i) { return i + (i >> 5); }
+
 // tw[i] = e^{-2 pi i i / FFT_L}, filled by every workgroup (8 values per thread)
 DEVI void fill_twiddles(cf* tw) {
 #pragma unroll
@@ -85,25 +91,25 @@ DEVI void twiddle(cf* v, int k, int span, const cf* tw) {   // v[r] *= e^{-2 pi 
 
 // Forward DFT of the 2048 values x[t + 256 r] that thread t holds in v[r].
 // On return thread t holds X[j + 512 r] (r = 0..3) in v[0..3] for j = t and
-// in v[4..7] for j = t + 256.  lds: 2048 entries; tw: the twiddle table (filled
+// in v[4..7] for j = t + 256.  lds: LDS_L entries (padded, lp); tw: the twiddle table (filled
 // before a barrier the first stage passes); ends with a barrier.
 DEVI void fft2048(cf* v, cf* lds, const cf* tw) {
     const int t = threadIdx.x;
     dft8(v);   // stage Ns = 1: outputs to 8 t + r
 #pragma unroll
-    for (int r = 0; r < 8; ++r) lds[8 * t + r] = v[r];
+    for (int r = 0; r < 8; ++r) lds[lp(8 * t + r)] = v[r];
     __syncthreads();
 #pragma unroll
     for (int Ns = 8; Ns <= 64; Ns *= 8) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = lds[t + FT * r];
+        for (int r = 0; r < 8; ++r) v[r] = lds[lp(t + FT * r)];
         const int k = t % Ns;
         twiddle<8>(v, k, Ns * 8, tw);
         dft8(v);
         __syncthreads();
         const int base = (t / Ns) * Ns * 8 + k;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) lds[base + r * Ns] = v[r];
+        for (int r = 0; r < 8; ++r) lds[lp(base + r * Ns)] = v[r];
         __syncthreads();
     }
     // stage Ns = 512, radix 4: butterflies t and t + 256
@@ -112,7 +118,7 @@ DEVI void fft2048(cf* v, cf* lds, const cf* tw) {
         const int j = t + FT * h;
         cf* w = v + 4 * h;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) w[r] = lds[j + 512 * r];
+        for (int r = 0; r < 4; ++r) w[r] = lds[lp(j + 512 * r)];
         twiddle<4>(w, j, 2048, tw);
         dft4(w);
     }
@@ -133,7 +139,7 @@ DEVI void fold_partials(double* part, const Fold4& f, double* red) {
 
 // conj(DFT(w zero-padded to FFT_L)) of k correlation-order taps
 __global__ __launch_bounds__(FT) void k_conv_spectrum(const float* w, int k, float2* spec) {
-    __shared__ cf lds[FFT_L];
+    __shared__ cf lds[LDS_L];
     __shared__ cf tw[FFT_L];
     const int t = threadIdx.x;
     fill_twiddles(tw);
@@ -153,7 +159,7 @@ __global__ __launch_bounds__(FT) void k_conv_spectrum(const float* w, int k, flo
 template <int FOLD>
 __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int adj, int out, int in, int base,
                                                  double sigma, int gate) {
-    __shared__ cf lds[FFT_L];
+    __shared__ cf lds[LDS_L];
     __shared__ cf tw[FFT_L];
     __shared__ double red[4 * (FT / 64)];
     Fold4 f{0.0, 0.0, 0.0, 0.0};
@@ -209,11 +215,11 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         for (int r = 0; r < 4; ++r) {
             const int j = t + FT * h + 512 * r;
             const cf p = cmul(v[4 * h + r], cf{sp[2 * j], sp[2 * j + 1]});
-            lds[j] = {p.x, -p.y};
+            lds[lp(j)] = {p.x, -p.y};
         }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = lds[t + FT * r];
+    for (int r = 0; r < 8; ++r) v[r] = lds[lp(t + FT * r)];
     __syncthreads();
     fft2048(v, lds, tw);
     // conj(result) / L: real part = window a, imaginary part = window b.

@@ -15,6 +15,8 @@ namespace cgs {
 // the compiler cannot infer their address space; they are declared global
 // (address space 1) to get global (not flat) memory instructions.
 template <typename T> using gptr = __attribute__((address_space(1))) T*;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- helpers
 template <typename T>
@@ -114,12 +116,33 @@ DEVI void block_sumN(double (&s)[N], double* sh) {
     __syncthreads();
 }
 
+// A thread's share of a fixed-order sum of p[stride i], i in [t0, t1): the
+// elements t0 + threadIdx.x + NT r in increasing r, loaded U at a time so that
+// U loads are in flight together (one at a time, each load of the loop would
+// wait for the previous one's add).  An index past t1 loads p[stride t0] and
+// is not added.
+template <int NT, int U>
+DEVI double thread_sum(const double* p, int64_t t0, int64_t t1, int64_t stride) {
+    double s = 0.0;
+    for (int64_t b = t0; b < t1; b += (int64_t)NT * U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = b + (int64_t)u * NT + threadIdx.x;
+            v[u] = p[stride * (i < t1 ? i : t0)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (b + (int64_t)u * NT + threadIdx.x < t1) s += v[u];
+    }
+    return s;
+}
+
 // Fixed-order sum of partial slot j over tiles [t0, t1) (partials of the
 // previous kernel: the kernel boundary makes them visible).
 template <int NT>
 DEVI double sum_parts(const double* part, int t0, int t1, int j, double* sh) {
-    double s = 0.0;
-    for (int i = t0 + (int)threadIdx.x; i < t1; i += NT) s += part[4 * (int64_t)i + j];
+    const double s = thread_sum<NT, 4>(part + j, t0, t1, 4);
     return block_sum<NT>(s, sh);
 }
 
@@ -150,12 +173,8 @@ DEVI double inst_xsum(const Tables& tb, const InstDesc& d, int j, double* sh) {
 
 // All four X-tile partial slots of the instance at once (sh: 4 * VEC_NT / 64).
 DEVI void inst_xsum4(const Tables& tb, const InstDesc& d, double (&s)[4], double* sh) {
-    s[0] = s[1] = s[2] = s[3] = 0.0;
-    for (int i = d.xt0 + (int)threadIdx.x; i < d.xt1; i += VEC_NT) {
-        const double* pp = tb.xpart + 4 * (int64_t)i;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) s[j] += pp[j];
-    }
+    for (int j = 0; j < 4; ++j) s[j] = thread_sum<VEC_NT, 4>(tb.xpart + j, d.xt0, d.xt1, 4);
     block_sum4<VEC_NT>(s, sh);
 }
 
@@ -169,26 +188,37 @@ DEVI void inst_csum4(const Tables& tb, const InstDesc& d, double (&s)[4], bool s
     double a[12];
 #pragma unroll
     for (int j = 0; j < 12; ++j) a[j] = 0.0;
-    for (int i = d.cp0 + (int)threadIdx.x; i < d.cp1; i += VEC_NT) {
-        const double* pp = tb.cpart + 4 * (int64_t)i;
+    // each thread's records of a range, U at a time, loaded before any is
+    // added (a record past the range's end loads its first one, not added)
+    auto range = [&](int lo, int hi, double* acc) {
+        constexpr int U = 2;
+        for (int b0 = lo; b0 < hi; b0 += U * VEC_NT) {
+            f64x2 c[U][2], q[U];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a[j] += pp[j];
-        if (start) {
-            const double* qq = tb.spart + 4 * (int64_t)i;
-            a[4] += qq[0];
-            a[5] += qq[1];
-        }
-    }
-    for (int i = d.ip0 + (int)threadIdx.x; i < d.ip1; i += VEC_NT) {
-        const double* pp = tb.cpart + 4 * (int64_t)i;
+            for (int u = 0; u < U; ++u) {
+                const int i = b0 + u * VEC_NT + (int)threadIdx.x;
+                const int k = i < hi ? i : lo;
+                const f64x2* pc = reinterpret_cast<const f64x2*>(tb.cpart + 4 * (int64_t)k);
+                c[u][0] = pc[0];
+                c[u][1] = pc[1];
+                if (start) q[u] = *reinterpret_cast<const f64x2*>(tb.spart + 4 * (int64_t)k);
+            }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a[6 + j] += pp[j];
-        if (start) {
-            const double* qq = tb.spart + 4 * (int64_t)i;
-            a[10] += qq[0];
-            a[11] += qq[1];
+            for (int u = 0; u < U; ++u) {
+                if (b0 + u * VEC_NT + (int)threadIdx.x >= hi) continue;
+                acc[0] += c[u][0][0];
+                acc[1] += c[u][0][1];
+                acc[2] += c[u][1][0];
+                acc[3] += c[u][1][1];
+                if (start) {
+                    acc[4] += q[u][0];
+                    acc[5] += q[u][1];
+                }
+            }
         }
-    }
+    };
+    range(d.cp0, d.cp1, a);
+    range(d.ip0, d.ip1, a + 6);
     block_sumN<VEC_NT, 12>(a, sh);
 #pragma unroll
     for (int j = 0; j < 4; ++j) s[j] = a[j] + a[6 + j];
@@ -236,9 +266,7 @@ DEVI XYTile xy_tile(const Tables& tb) {
     return r;
 }
 
-// 16-byte vector access helpers (native clang vector types)
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
+// 16-byte vector access helpers (native clang vector types: f32x4, f64x2 above)
 template <typename T> struct Vec16;
 template <> struct Vec16<float> { using type = f32x4; static constexpr int W = 4; };
 template <> struct Vec16<double> { using type = f64x2; static constexpr int W = 2; };
@@ -247,6 +275,43 @@ template <typename T>
 DEVI void vec_get(const typename Vec16<T>::type& v, T* o) {
 #pragma unroll
     for (int e = 0; e < Vec16<T>::W; ++e) o[e] = v[e];
+}
+
+// ---------------------------------------------------------------- vector chunks
+// A thread's elements of a vector tile [lo, hi): NCH chunks of four
+// consecutive elements, chunk j starting at c0 + 4 (threadIdx.x + VEC_NT j)
+// with c0 = lo rounded down to 4.  The tile builder keeps every tile within
+// NCH * VEC_NT chunks (a tile that starts off the 4-element grid is shortened
+// by the offset), and vectors are padded to XY_ALIGN elements, so a chunk that
+// holds an element of the tile lies inside its vector.  A chunk without one is
+// loaded at c0 (its values are never used) and not stored.
+template <typename T> using v4 = T __attribute__((ext_vector_type(4)));
+constexpr int NCH = VEC_TILE / (4 * VEC_NT);
+static_assert(NCH * 4 * VEC_NT == VEC_TILE, "chunks per thread");
+struct Chunks {
+    int64_t lo, hi, c0;
+    DEVI Chunks(int64_t lo_, int64_t hi_) : lo(lo_), hi(hi_), c0(lo_ & ~int64_t(3)) {}
+    DEVI int64_t at(int j) const { return c0 + 4 * ((int64_t)threadIdx.x + (int64_t)VEC_NT * j); }
+    DEVI bool any(int j) const { return at(j) < hi; }   // (at(j) + 4 > lo always)
+    DEVI int64_t ld_at(int j) const { return any(j) ? at(j) : c0; }
+    DEVI bool full(int j) const { const int64_t i = at(j); return i >= lo && i + 4 <= hi; }
+    DEVI bool has(int j, int e) const { const int64_t i = at(j) + e; return i >= lo && i < hi; }
+};
+template <typename T>
+DEVI v4<T> ld4(gptr<const T> p, int64_t i) {
+    return *(gptr<const v4<T>>)(p + i);
+}
+template <typename T>
+DEVI void st4(gptr<T> p, const Chunks& c, int j, const v4<T>& v) {
+    if (!c.any(j)) return;
+    const int64_t i = c.at(j);
+    if (c.full(j)) {
+        *(gptr<v4<T>>)(p + i) = v;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (c.has(j, e)) p[i + e] = v[e];
 }
 
 // ---------------------------------------------------------------- operator: convolution

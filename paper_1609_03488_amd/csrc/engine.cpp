@@ -398,8 +398,13 @@ void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im
             sg.start = off;
             sg.len = qj;
             const int32_t sid = (int32_t)im.seg.size();
-            for (int64_t s = 0; s < qj; s += VEC_TILE)
-                im.yt.push_back(VecTile{ii, sid, off + s, (int32_t)std::min<int64_t>(VEC_TILE, qj - s), 0});
+            // a tile spans at most VEC_TILE elements of the 4-element grid
+            // (vector kernels walk tiles in aligned chunks of four)
+            for (int64_t s = 0; s < qj;) {
+                const int64_t len = std::min<int64_t>(VEC_TILE - ((off + s) & 3), qj - s);
+                im.yt.push_back(VecTile{ii, sid, off + s, (int32_t)len, 0});
+                s += len;
+            }
             sg.ntiles = (int32_t)im.yt.size() - sg.yt0;
             im.seg.push_back(sg);
             off += qj;
@@ -471,7 +476,7 @@ size_t image_work_bytes(const TableImage& im) {
     const size_t nfa = im.fadj.empty() ? 0 : im.fadj[0].size();
     return align256(4 * im.xt.size() * 8) + align256(4 * im.yt.size() * 8) +
            align256(2 * im.seg.size() * 8) + align256(im.seg.size() * 4) +
-           2 * align256(4 * (nfa + im.xt.size()) * 8) +
+           2 * align256(4 * (nfa + im.xt.size()) * 8) + align256(4 * (im.xt.size() + im.yt.size()) * 8) +
            align256(im.inst.size() * NSC * 8) + 256;
 }
 
@@ -680,6 +685,7 @@ int Engine::build(const std::vector<InstRec>& r) {
     T.seg_cnt = (int*)w; w += align256(im.seg.size() * 4);
     T.cpart = (double*)w; w += align256(4 * ((im.fadj.empty() ? 0 : im.fadj[0].size()) + im.xt.size()) * 8);
     T.spart = (double*)w; w += align256(4 * ((im.fadj.empty() ? 0 : im.fadj[0].size()) + im.xt.size()) * 8);
+    T.tpart = (double*)w; w += align256(4 * (im.xt.size() + im.yt.size()) * 8);
     gather_dev = (double*)w;
     if (!im.seg.empty()) CGS_HIP(hipMemsetAsync(T.seg_cnt, 0, im.seg.size() * 4, stream));
     T.nx_tiles = (int)im.xt.size();
@@ -741,7 +747,7 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         c.part = T.cpart;
         conv(c, 1, XQ, YT, XP, 1.0, G_ADMM);
         launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
-                         CgStart{st.cg_tol, st.cg_rate, st.cg_floor, 1, 1});
+                         CgStart{st.cg_tol, st.cg_rate, st.cg_floor, 1, 1, 1, st.alpha});
         return;
     }
     apply(0, YT, XP, -1, 1.0, gate);
@@ -756,8 +762,9 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         c.part = T.cpart;
         conv(c, 1, XQ, YT, XP, 1.0, gate);
         // (on the ADMM path the update that ends CG also takes the tau products)
+        const int tau = gate == G_ADMM_CG && track ? 1 : 0;
         launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
-                         CgStart{0.0, 0.0, 0.0, 0, gate == G_ADMM_CG && track ? 1 : 0});
+                         CgStart{0.0, 0.0, 0.0, 0, tau, tau, st.alpha});
         return;
     }
     apply(1, XQ, YT, XP, 1.0, gate);
@@ -792,8 +799,12 @@ void Engine::admm_step() {
         for (int i = 0; i < cg_launch; ++i)
             cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == cg_launch - 1);
     }
-    if (!folded_cg())                                            // (else in the last CG update)
-        launch_tau_dots(prec, T, st.alpha, 1, stream);           // z_y = w_y + A z; c^T z_x + b^T z_y
+    if (folded_cg()) {
+        // z_y, the tau products and the cone terms came from the last CG update
+        launch_project(prec, T, st.alpha, stream, 1);            // relax, project, dual update
+        return;
+    }
+    launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; c^T z_x + b^T z_y
     launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
 }
@@ -1009,6 +1020,8 @@ void Engine::fill_info(int i, cgs_info* info) const {
     info->res_pri = sc[SC_RP];
     info->res_dual = sc[SC_RD];
     info->gap = sc[SC_GAP];
+    info->cert_precision = precision;
+    info->reserved_ = 0;
 }
 
 }  // namespace cgs

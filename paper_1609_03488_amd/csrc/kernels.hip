@@ -198,7 +198,159 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
 // The scalar products of u~_tau for one tile (Section V-B: the tau component
 // of the subspace projection): c^T z_x over an X tile, or z_y = w_y + A z
 // (the carried product) stored and b^T z_y over a Y tile; FP64 partial in
-// slot 0 of the tile's X or Y partials.
+// slot 0 of the tile's X or Y partials.  With CgStart::cone the cone terms of
+// the projection that follows are formed as well (see CgStart).
+//
+// The element work of the update that ends an instance's CG, and of a CG
+// update that goes on, in one routine: `upd` = 0 leaves z and A z as they are
+// (a step whose CG ran no update) and only does the tau (and cone) work.
+// Every thread loads its chunks of every vector it needs before the first
+// arithmetic, then stores.
+template <typename T>
+DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<const double> sc,
+                   const CgStart& cs, bool upd, double al, double be, bool more, bool track, bool tw,
+                   int z, int r, int p, int q, double* sh) {
+    // One chunk at a time (all its loads, then the arithmetic, then its
+    // stores): holding every chunk of every vector at once needs more
+    // registers than let all of a launch's workgroups be resident together.
+    const Chunks ck(xt.t.start, xt.t.start + xt.t.len);
+    if (!xt.is_y) {
+        gptr<T> zp = xvec<T>(d, z);
+        gptr<T> rp = xvec<T>(d, r);
+        gptr<T> pp = xvec<T>(d, p);
+        gptr<const T> qp = xvec<T>(d, q);
+        gptr<T> kp = xvec<T>(d, XK);
+        gptr<const T> cp = xvec<T>(d, XC);
+        double s0 = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < NCH; ++j) {
+            if (!ck.any(j)) break;
+            const int64_t i = ck.at(j);
+            v4<T> zv = ld4<T>(zp, i), qv, pv, rv, kv, cv;
+            if (upd) {
+                qv = ld4<T>(qp, i);
+                pv = ld4<T>(pp, i);
+                if (more) rv = ld4<T>(rp, i);
+                if (track) kv = ld4<T>(kp, i);
+            }
+            if (tw) cv = ld4<T>(cp, i);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (upd) {
+                    const double qi = (double)qv[e], pi = (double)pv[e];
+                    zv[e] = (T)fma(al, pi, (double)zv[e]);
+                    if (more) {
+                        const T ri = (T)fma(-al, qi, (double)rv[e]);
+                        rv[e] = ri;
+                        pv[e] = (T)fma(be, pi, (double)ri);
+                    }
+                    if (track) kv[e] = (T)fma(al, qi, (double)kv[e]);
+                }
+                if (tw && ck.has(j, e)) s0 = fma((double)cv[e], (double)zv[e], s0);
+            }
+            if (upd) {
+                // (once CG has ended, r is dead: the next solve forms it afresh)
+                st4<T>(zp, ck, j, zv);
+                if (more) {
+                    st4<T>(rp, ck, j, rv);
+                    st4<T>(pp, ck, j, pv);
+                }
+                if (track) st4<T>(kp, ck, j, kv);
+            }
+        }
+        if (tw) {
+            s0 = block_sum<VEC_NT>(s0, sh);
+            if (threadIdx.x == 0) {
+                double* part = tb.xpart + 4 * (int64_t)xt.index;
+                if (cs.cone) tb.tpart[xt.index] = s0;
+                else part[0] = s0;
+                if (cs.cone && xt.index == d.xt0) {
+                    // for the projection: the expansion point and tau + kappa
+                    // (it rewrites tau and kappa while its workgroups run)
+                    const double ex = sc[SC_UT];
+                    part[1] = std::isfinite(ex) ? ex : 0.0;
+                    part[2] = sc[SC_TAU] + sc[SC_KAPPA];
+                }
+            }
+        }
+        return;
+    }
+    gptr<T> azp = yvec<T>(d, YA);
+    gptr<const T> app = yvec<T>(d, YT);
+    gptr<const T> wyp = yvec<T>(d, YW);
+    gptr<const T> bp = yvec<T>(d, YB);
+    gptr<T> zyp = yvec<T>(d, YZ);
+    gptr<const T> uyp = yvec<T>(d, YU);
+    gptr<const T> vsp = yvec<T>(d, YV);
+    gptr<const T> gyp = yvec<T>(d, YG);
+    const bool cone = tw && cs.cone && xt.t.seg >= 0;
+    double e_pt = 0.0;
+    int64_t head = -1;
+    if (cone) {
+        const double ex = sc[SC_UT];
+        e_pt = std::isfinite(ex) ? ex : 0.0;
+        head = tb.seg[xt.t.seg].start;
+    }
+    const double alpha = cs.alpha;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int j = 0; j < NCH; ++j) {
+        if (!ck.any(j)) break;
+        const int64_t i = ck.at(j);
+        v4<T> av = ld4<T>(azp, i), apv, wv, bv, uv, vv, gv;
+        if (upd) apv = ld4<T>(app, i);
+        if (tw) {
+            wv = ld4<T>(wyp, i);
+            bv = ld4<T>(bp, i);
+        }
+        if (cone) {
+            uv = ld4<T>(uyp, i);
+            vv = ld4<T>(vsp, i);
+            gv = ld4<T>(gyp, i);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (upd) av[e] = (T)fma(al, (double)apv[e], (double)av[e]);
+            if (!tw) continue;
+            const T zy = (T)((double)wv[e] + (double)av[e]);
+            wv[e] = zy;   // (w_y is not needed again: the register holds z_y)
+            if (!ck.has(j, e)) continue;
+            s[0] = fma((double)bv[e], (double)zy, s[0]);
+            if (cone) {
+                const double g = (double)gv[e];
+                const double a = alpha * (double)zy + (1.0 - alpha) * (double)uv[e] - (double)vv[e] -
+                                 alpha * e_pt * g;
+                const double b = alpha * g;
+                if (i + e == head) {
+                    tb.seg_val[2 * xt.t.seg] = a;
+                    tb.seg_val[2 * xt.t.seg + 1] = b;
+                } else {
+                    s[1] = fma(a, a, s[1]);
+                    s[2] = fma(a, b, s[2]);
+                    s[3] = fma(b, b, s[3]);
+                }
+            }
+        }
+        if (upd) st4<T>(azp, ck, j, av);
+        if (tw) st4<T>(zyp, ck, j, wv);
+    }
+    if (!tw) return;
+    const int64_t ntl = (int64_t)tb.nx_tiles + tb.ny_tiles, b = (int64_t)tb.nx_tiles + xt.index;
+    if (cone) {
+        block_sum4<VEC_NT>(s, sh);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tb.tpart[j * ntl + b] = s[j];
+        }
+    } else {
+        s[0] = block_sum<VEC_NT>(s[0], sh);
+        if (threadIdx.x == 0) {
+            if (cs.cone) tb.tpart[b] = s[0];
+            else tb.ypart[4 * (int64_t)xt.index] = s[0];
+        }
+    }
+}
+
 template <typename T>
 DEVI void tau_tile(const Tables& tb, const InstDesc& d, const XYTile& xt, double* sh) {
     gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
@@ -260,7 +412,7 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
             sc[SC_CGACT] = act ? 1.0 : 0.0;
         }
         if (!act) {
-            if (cs.tau) tau_tile<T>(tb, d, xt, sh);
+            if (cs.tau) cg_elems<T>(tb, d, xt, sc, cs, false, 0.0, 0.0, false, false, true, z, r, p, q, sh);
             return;
         }
     } else {
@@ -293,53 +445,8 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_update(Tables tb, int z, int r, i
     // the step's last CG update also does the work of k_tau_dots on the final
     // z and A z (cs.tau: every instance's CG ends in an update of this loop)
     const bool tw = cs.tau && !more;
-    if (!ok) {
-        if (tw) tau_tile<T>(tb, d, xt, sh);
-        return;
-    }
-    const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
-    double s0 = 0.0;
-    if (!xt.is_y) {
-        gptr<T> zv = xvec<T>(d, z);
-        gptr<T> rv = xvec<T>(d, r);
-        gptr<T> pv = xvec<T>(d, p);
-        gptr<const T> qv = xvec<T>(d, q);
-        gptr<T> kz = xvec<T>(d, XK);
-        gptr<const T> cv = xvec<T>(d, XC);
-        // (once CG has ended, r is dead: the next solve forms it afresh)
-        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            const double qi = (double)qv[i], pi = (double)pv[i];
-            const T zi = (T)fma(al, pi, (double)zv[i]);
-            zv[i] = zi;
-            if (more) {
-                const T ri = (T)fma(-al, qi, (double)rv[i]);
-                rv[i] = ri;
-                pv[i] = (T)fma(be, pi, (double)ri);
-            }
-            if (track) kz[i] = (T)fma(al, qi, (double)kz[i]);
-            if (tw) s0 = fma((double)cv[i], (double)zi, s0);
-        }
-    } else {
-        gptr<T> az = yvec<T>(d, YA);
-        gptr<const T> ap = yvec<T>(d, YT);
-        gptr<const T> wy = yvec<T>(d, YW);
-        gptr<const T> bv = yvec<T>(d, YB);
-        gptr<T> zy = yvec<T>(d, YZ);
-        for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
-            const T ai = (T)fma(al, (double)ap[i], (double)az[i]);
-            az[i] = ai;
-            if (tw) {
-                const T v = (T)((double)wy[i] + (double)ai);
-                zy[i] = v;
-                s0 = fma((double)bv[i], (double)v, s0);
-            }
-        }
-    }
-    if (tw) {
-        s0 = block_sum<VEC_NT>(s0, sh);
-        double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
-        if (threadIdx.x == 0) part[0] = s0;
-    }
+    if ((!ok || (xt.is_y && !track)) && !tw) return;
+    cg_elems<T>(tb, d, xt, sc, cs, ok, al, be, more, track != 0, tw, z, r, p, q, sh);
 }
 
 template <typename T>
@@ -443,15 +550,55 @@ __global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
-    __shared__ double sh[VEC_NT / 64];
+__global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha, int cone) {
+    __shared__ double sh[4 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
-    const double ut = sc[SC_UT];
+    const int seg = xt.is_y ? xt.t.seg : -1;
+    YbarTile<T> yb;
+    if (seg >= 0 && !cone) yb.load(d, xt.t);   // (in flight during the sums)
+    double ut, t = 0.0, nz = 0.0;
+    if (cone) {
+        // u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta from the slot-0
+        // partials (Tables::tpart) of every X and Y tile of the instance, and the cone's head
+        // value and tail norm from the cone terms (CgStart::cone), all summed
+        // in one fixed order by every workgroup
+        const double* xp0 = tb.xpart + 4 * (int64_t)d.xt0;
+        const double e_pt = xp0[1], wtau = xp0[2];
+        const int64_t ntl = (int64_t)tb.nx_tiles + tb.ny_tiles;
+        const double* ty = tb.tpart + tb.nx_tiles;   // slot 0 of the Y tiles
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        s[0] = thread_sum<VEC_NT, 4>(tb.tpart, d.xt0, d.xt1, 1) + thread_sum<VEC_NT, 4>(ty, d.yt0, d.yt1, 1);
+        double ah = 0.0, bh = 0.0;
+        if (seg >= 0) {
+            const SocSeg sg = tb.seg[seg];
+            ah = tb.seg_val[2 * seg];
+            bh = tb.seg_val[2 * seg + 1];
+#pragma unroll
+            for (int j = 1; j < 4; ++j)
+                s[j] = thread_sum<VEC_NT, 4>(ty + j * ntl, sg.yt0, sg.yt0 + sg.ntiles, 1);
+        }
+        block_sum4<VEC_NT>(s, sh);
+        ut = (wtau + s[0]) / sc[SC_ETA];
+        if (seg >= 0) {
+            const double dl = ut - e_pt;
+            t = ah - dl * bh;
+            const double n2 = s[1] - 2.0 * dl * s[2] + dl * dl * s[3];
+            nz = sqrt(n2 > 0.0 ? n2 : 0.0);
+        }
+    } else {
+        ut = sc[SC_UT];
+        if (seg >= 0) {
+            const SocSeg sg = tb.seg[seg];
+            t = tb.seg_val[2 * seg];
+            nz = sqrt(sum_parts_all<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 1, sh));
+        }
+    }
     if (!xt.is_y && xt.index == d.xt0 && threadIdx.x == 0) {
-        // tau, kappa of the step (no workgroup of this kernel reads them)
+        // tau, kappa of the step (no other workgroup of this kernel reads them)
+        if (cone) sc[SC_UT] = ut;
         const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
         const double ubar = alpha * ut + (1.0 - alpha) * tau;
         const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
@@ -473,7 +620,7 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
     gptr<T> uy = yvec<T>(d, YU);
     gptr<T> vs = yvec<T>(d, YV);
     gptr<T> wy = yvec<T>(d, YW);
-    if (xt.t.seg < 0) {
+    if (seg < 0) {
         for (int64_t i = lo + threadIdx.x; i < hi; i += VEC_NT) {
             double ub;
             const double pv = ybar_minus_v<T>(d, i, ut, alpha, ub);
@@ -485,11 +632,8 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
         }
         return;
     }
-    YbarTile<T> yb;
-    yb.load(d, xt.t);   // (in flight during the cone's norm sum)
-    const SocSeg sg = tb.seg[xt.t.seg];
-    const double t = tb.seg_val[2 * xt.t.seg];
-    const double nz = sqrt(sum_parts_all<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 1, sh));
+    const SocSeg sg = tb.seg[seg];
+    if (cone) yb.load(d, xt.t);
     // Pi(t, z): (t, z) if ||z|| <= t; 0 if ||z|| <= -t; ((t+||z||)/2)(1, z/||z||) otherwise
     int mode;
     double a = 0.0;
@@ -935,8 +1079,8 @@ void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st) {
     // every Y tile: u~_tau for all instances, cone partials where there are cones
     CGS_DISPATCH(prec, k_soc_prep, t.ny_tiles, VEC_NT, st, t, alpha);
 }
-void launch_project(int prec, const Tables& t, double alpha, hipStream_t st) {
-    CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
+void launch_project(int prec, const Tables& t, double alpha, hipStream_t st, int cone) {
+    CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha, cone);
 }
 void launch_resid(int prec, const Tables& t, double eps, int max_iters, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_resid, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, eps, max_iters, gate);

@@ -88,10 +88,22 @@ struct CgStart {
     // launch_tau_dots (form_zy = 1) on the final z and A z (folded ADMM path,
     // where some update of the loop always runs)
     int tau;
+    // with tau: that update also forms the cone terms of the projection that
+    // follows (launch_project with cone = 1; no launch_soc_prep): relative to
+    // the expansion point e = the previous step's u~_tau, every second-order
+    // cone row has u_bar - v = a - (u~_tau - e) b with
+    //   a = alpha z_y + (1 - alpha) u_y - v_s - alpha e g_y,   b = alpha g_y,
+    // so the cone's tail norm is sum a^2 - 2 (u~_tau - e) sum a b
+    // + (u~_tau - e)^2 sum b^2; the tau products go to slot 0 and the sums over
+    // the tail to slots 1..3 of Tables::tpart, the head's a and b to seg_val,
+    // and the first X tile's workgroup stores e and tau + kappa in its X
+    // partial slots 1 and 2
+    int cone;
+    double alpha;
 };
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
                       int gate, int track, hipStream_t st, int folded = 0, int last = 0,
-                      CgStart cs = CgStart{0.0, 0.0, 0.0, 0, 0});
+                      CgStart cs = CgStart{0.0, 0.0, 0.0, 0, 0, 0, 0.0});
 // (folded = 1: the partials come from the A^T launch of ConvLaunch::fold = 2;
 // last = 1: the step's last CG launch of a round run from a snapshot; when CG
 // would go on the instance is suspended, phase 3, for the host to run the
@@ -108,8 +120,11 @@ void launch_wy(int prec, const Tables& t, int gate, hipStream_t st);
 void launch_tau_dots(int prec, const Tables& t, double alpha, int form_zy, hipStream_t st);
 // head value and tail sum of squares of (u_bar_y - v_s) per second-order cone
 void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st);
-// relaxation, projection onto K, dual update of every X/Y entry
-void launch_project(int prec, const Tables& t, double alpha, hipStream_t st);
+// relaxation, projection onto K, dual update of every X/Y entry.  cone = 0:
+// u~_tau and the cone norms come from launch_soc_prep; cone = 1: every
+// workgroup forms u~_tau from the tau products' partials and the cone norms
+// from the cone terms of the update that ended CG (CgStart::cone)
+void launch_project(int prec, const Tables& t, double alpha, hipStream_t st, int cone = 0);
 // termination quantities from A u_x (in YT) and A^T u_y (in XT)
 void launch_resid(int prec, const Tables& t, double eps, int max_iters, int gate, hipStream_t st);
 

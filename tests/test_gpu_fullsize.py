@@ -1,11 +1,13 @@
 """GPU checks at the benchmark sizes, in the launch configuration bench.py uses.
 
-Exact optima come from tests/golden/reference_objectives.json (written by
-tests/golden/make_reference.py from the FP64 oracle only).  The n = 2^20
-deconvolution has no affordable exact optimum, so it is checked through
-properties that hold at any size: the KKT residuals of the returned point
-recomputed in FP64 on the host, and the objective bound ||noise|| (x_true is
-feasible).
+Reference values come from tests/golden/reference_objectives.json (written by
+tests/golden/make_reference.py from the FP64 oracle only): exact optima where
+the oracle can certify one, and the oracle's run of the same method to the
+same tolerance for the deconvolutions (at n = 2^20 the oracle's banded
+factorisation takes about 17 GB and its 620 iterations some 20 minutes).  The
+returned points are also checked through properties that hold at any size:
+the KKT residuals recomputed in FP64 on the host, and for deconvolution the
+objective bound ||noise|| (x_true is feasible).
 """
 import json
 import os
@@ -57,17 +59,26 @@ def test_deconv_n1M_k1025_fp32(engine):
     f = o.deconv_objective(d["c"], d["b"], x[:cfg["n"]])
     noise = np.linalg.norm(d["b"] - np.convolve(d["c"], d["x_true"]))
     assert f <= noise * (1 + 1e-4), (f, noise)
+    # the oracle's run of the same method to the same eps and scaling
+    same = REF[cfg["name"] + "_scs"]
+    assert (same["eps"], same["normalize"]) == (cfg["eps"], 1)
+    assert abs(f - same["objective"]) / same["objective"] <= 1e-4, (f, same["objective"])
     # dual side: y in K (cone membership of the returned dual point)
     assert o.in_cone(y, prog.l, prog.q, 1e-6 * (1 + np.abs(y).max()))
 
 
-def test_deconv_n1000_k101_fp64_against_exact_nnls():
+def test_deconv_n1000_k101_fp64_at_its_tolerance():
+    """The n = 1000 deconvolution at its own tolerance 1e-6 in FP64, with block
+    equilibration (normalize = 2: data scaling alone needs tens of thousands of
+    iterations here).  Residuals of the returned point recomputed in FP64 are
+    within 1e-6; the natural objective is within 1e-4 of the oracle's run of
+    the same method to the same tolerance and scaling, and within 1e-4 of the
+    exact optimum (Lawson-Hanson), both stored by make_reference.py."""
     cfg = w.workload("deconv_n1000_k101")
-    _say(cfg["name"])
+    _say(cfg["name"], "eps", cfg["eps"])
     d = w.make_deconv(cfg)
     pr = P.deconv_problem(d["c"], d["b"])
-    # 1e-6 is out of reach of the method in 1e5 iterations; check 1e-4
-    st = P.Settings.make(precision=P.FP64, eps=1e-4, check_every=10)
+    st = P.Settings.make(precision=P.FP64, eps=cfg["eps"], check_every=10, normalize=2)
     s = P.Solver(pr.op, pr.l, pr.q, st)
     s.set_data(0, pr.b, pr.c)
     info = s.solve()[0]
@@ -75,23 +86,27 @@ def test_deconv_n1000_k101_fp64_against_exact_nnls():
     x, y, sl = s.solution(0)
     prog = o.deconv_program(d["c"], d["b"])
     rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
-    assert max(rp, rd, gap) <= 1.05e-4
-    f = o.deconv_objective(d["c"], d["b"], x[:1000])
-    fref = o.scs_solve(prog, eps=1e-4, check_every=10)
-    fo = o.deconv_objective(d["c"], d["b"], fref.x[:1000])
-    assert abs(f - fo) / fo <= 1e-4, (f, fo)
+    assert max(rp, rd, gap) <= 1.05 * cfg["eps"], (rp, rd, gap)
+    f = o.deconv_objective(d["c"], d["b"], x[:cfg["n"]])
+    same = REF["deconv_n1000_k101_scs"]
+    assert (same["eps"], same["normalize"]) == (cfg["eps"], 2)
+    assert abs(f - same["objective"]) / same["objective"] <= 1e-4, (f, same["objective"])
     exact = REF[cfg["name"]]["objective"]
-    assert exact <= f and (f - exact) / exact < 5e-3
+    assert exact * (1 - 1e-12) <= f and (f - exact) / exact <= 1e-4, (f, exact)
 
 
-def test_lasso_5000x10000_fp32_against_exact():
+@pytest.mark.parametrize("prec", [P.FP32, P.FP64], ids=["fp32", "fp64"])
+def test_lasso_5000x10000_against_exact(prec):
+    """The dense lasso at the settings bench.py runs (block equilibration,
+    normalize = 2; stop at the workload's stop_eps = 1e-5), in FP32 and FP64:
+    residuals of the returned point recomputed in FP64 within the stop, and the
+    objective within 1e-4 of the KKT-certified optimum."""
     import torch
     cfg = w.workload("lasso_5000x10000")
-    _say(cfg["name"])
+    _say(cfg["name"], prec)
     d = w.make_lasso(cfg)
     pr = P.lasso_problem(d["A"], d["b"], d["lam"])
-    # a 1e-4 stop leaves the objective ~1e-4 off (1.2e-4 measured); 1e-5 for the bar
-    st = P.Settings.make(precision=P.FP32, eps=cfg["eps"] / 10, check_every=10)
+    st = P.Settings.make(precision=prec, eps=cfg["stop_eps"], check_every=10, normalize=2)
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=torch.cuda.Stream())
     s.set_data(0, pr.b, pr.c)
     info = s.solve()[0]
@@ -99,34 +114,40 @@ def test_lasso_5000x10000_fp32_against_exact():
     x, y, sl = s.solution(0)
     prog = o.lasso_program(d["A"], d["b"], d["lam"])
     rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
-    assert max(rp, rd, gap) <= 1.05e-4, (rp, rd, gap)
+    assert max(rp, rd, gap) <= 1.05 * cfg["stop_eps"], (rp, rd, gap)
     f = o.lasso_objective(d["A"], d["b"], float(d["lam"]), x[:cfg["n"]])
     exact = REF[cfg["name"]]["objective"]
     assert abs(f - exact) / exact <= 1e-4, (f, exact)
 
 
 def test_lasso_batch64_bf16_against_exact():
+    """The batch at the settings bench.py runs (BF16 products, block
+    equilibration, stop_eps = 1e-5): every one of the 64 instances is solved,
+    certified by the residual test on the FP32 operator, has FP64 residuals
+    within the stop and an objective within 1e-4 of its KKT-certified optimum."""
     import torch
     cfg = w.workload("lasso_batch64_2000x8000")
     _say(cfg["name"])
     d = w.make_lasso_batch(cfg)
     B = cfg["batch"]
     prs = [P.lasso_problem(d["A"], d["b"][i], d["lam"][i]) for i in range(B)]
-    # stops at eps / 10 so that the objective lands within 1e-4 of the optimum
-    st = P.Settings.make(precision=P.BF16, eps=cfg["eps"] / 10, check_every=10)
+    st = P.Settings.make(precision=P.BF16, eps=cfg["stop_eps"], check_every=10, normalize=2)
     s = P.Solver(prs[0].op, prs[0].l, prs[0].q, st, batch=B, stream=torch.cuda.Stream())
     for i, pr in enumerate(prs):
         s.set_data(i, pr.b, pr.c)
     infos = s.solve()
     assert all(inf["status"] == P.SOLVED for inf in infos), [inf["status"] for inf in infos]
-    for key, ref in REF[cfg["name"]].items():
-        i = int(key)
+    assert all(inf["cert_precision"] == P.FP32 for inf in infos)
+    refs = REF[cfg["name"]]
+    assert len(refs) == B
+    for i in range(B):
         x, y, sl = s.solution(i)
         prog = o.lasso_program(d["A"], d["b"][i], d["lam"][i])
         rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
-        assert max(rp, rd, gap) <= 1e-4, (i, rp, rd, gap)
+        assert max(rp, rd, gap) <= 1.05 * cfg["stop_eps"], (i, rp, rd, gap)
         f = o.lasso_objective(d["A"], d["b"][i], d["lam"][i], x[:cfg["n"]])
-        assert abs(f - ref["objective"]) / ref["objective"] <= 1e-4, (i, f, ref["objective"])
+        ref = refs[str(i)]["objective"]
+        assert abs(f - ref) / ref <= 1e-4, (i, f, ref)
 
 
 @pytest.mark.parametrize("name", ["regls_dense_6000x3000", "regls_conv_3000_k1365"])

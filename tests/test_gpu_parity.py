@@ -395,22 +395,26 @@ def _spec_cases():
             ("lasso_300x900", P.lasso_problem(A, d3["b"], d3["lam"]))]
 
 
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
 @pytest.mark.parametrize("prec", [P.FP64, P.FP32], ids=["fp64", "fp32"])
-def test_predicted_cg_launches_equal_full_launches(prec):
+def test_predicted_cg_launches_equal_full_launches(prec, graph):
     """cg_adaptive = 1 runs each check interval with the previous interval's
     most CG iterations per step as launches and runs an interval again from
     its snapshot when a step needed more; the iterates must equal those of
     cg_adaptive = 0 (cg_max_iters launches every step) bit for bit.  A fast
     tightening CG tolerance (cg_rate 3) makes the per-step need grow, so some
-    interval is run again."""
+    interval is run again.  With a stream the intervals are captured and
+    replayed as graphs (snapshot, suspension and rerun included)."""
+    import torch
     reruns = 0
     for name, pr in _spec_cases():
         for rate in (1.5, 3.0):
-            _say("predicted cg launches", name, prec, rate)
+            _say("predicted cg launches", name, prec, rate, "graph" if graph else "direct")
             out = {}
             for ad in (0, 1):
-                s = _solver(pr, prec, eps=1e-5, check_every=10, fused_max=0, cg_rate=rate,
-                            cg_floor=1e-9, max_iters=3000, cg_adaptive=ad)
+                st = P.Settings.make(precision=prec, eps=1e-5, check_every=10, fused_max=0, cg_rate=rate,
+                                     cg_floor=1e-9, max_iters=3000, cg_adaptive=ad)
+                s = P.Solver(pr.op, pr.l, pr.q, st, stream=torch.cuda.Stream() if graph else None)
                 s.set_data(0, pr.b, pr.c)
                 info = s.solve()[0]
                 out[ad] = (info, s.solution(0), s.rounds())
@@ -424,11 +428,13 @@ def test_predicted_cg_launches_equal_full_launches(prec):
     assert reruns > 0
 
 
-def test_predicted_cg_launches_batch_equal_full_launches():
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+def test_predicted_cg_launches_batch_equal_full_launches(graph):
     """The same with three instances in one solver: an interval that one
     instance needs to run again is run again for all of them (each restored from
     its own copy), and every instance's iterates equal those of
     cg_adaptive = 0 bit for bit."""
+    import torch
     A = w.lasso_matrix(300, 900, 41)
     insts = [w.lasso_instance(300, 900, 0.05, 1e-4, 4100 + i, A=A, matrix_seed=41) for i in range(3)]
     prs = [P.lasso_problem(A, d["b"], d["lam"]) for d in insts]
@@ -437,8 +443,10 @@ def test_predicted_cg_launches_batch_equal_full_launches():
         _say("predicted cg launches, batch", rate)
         out = {}
         for ad in (0, 1):
-            s = _solver(prs[0], P.FP32, batch=3, eps=1e-5, check_every=10, fused_max=0, cg_rate=rate,
-                        cg_floor=1e-9, max_iters=2000, cg_adaptive=ad)
+            st = P.Settings.make(precision=P.FP32, eps=1e-5, check_every=10, fused_max=0, cg_rate=rate,
+                                 cg_floor=1e-9, max_iters=2000, cg_adaptive=ad)
+            s = P.Solver(prs[0].op, prs[0].l, prs[0].q, st, batch=3,
+                         stream=torch.cuda.Stream() if graph else None)
             for i, pr in enumerate(prs):
                 s.set_data(i, pr.b, pr.c)
             infos = s.solve()
@@ -489,6 +497,35 @@ def test_server_result_same_alone_and_in_mix():
         assert ia["status"] == P.SOLVED and im["status"] == P.SOLVED
         assert ia["iters"] == im["iters"]
         np.testing.assert_array_equal(xa, xm)
+
+
+def test_server_results_match_oracle():
+    """Served results against the oracle: a seeded Poisson trace with the
+    serving workload's recipe (Section V-C deconvolution; log-uniform n, odd
+    Gaussian kernels of length k with sigma = k / 7, 5 % nonzeros, noise
+    variance 1e-4) at sizes the oracle solves in seconds, replayed through the
+    continuous-batching server with fused (one workgroup) and one-launch-per-
+    kernel requests in the same rounds.  Every request is solved and its
+    natural objective is within 1e-4 of the oracle's run of the same method to
+    the same eps (FP64, exact subspace solves, data scaling)."""
+    from paper_1609_03488_amd.serve import replay
+    _say("server vs oracle")
+    trace = w.serving_trace(count=10, rate=400.0, seed=2005, n_lo=600, n_hi=4000, k_half_lo=5,
+                            k_half_hi=60)
+    data = {r.rid: w.serving_request_data(r) for r in trace}
+    probs = {rid: P.deconv_problem(d["c"], d["b"]) for rid, d in data.items()}
+    st = P.Settings.make(precision=P.FP32, eps=1e-4, check_every=10, cg_max_iters=3, fused_max=4000)
+    res = replay(trace, lambda r: probs[r.rid], settings=st, workspace_bytes=256 << 20,
+                 steps_per_call=10, keep_x=True)
+    assert res["completed"] == len(trace) and res["solved"] == len(trace), res["solved"]
+    for c in res["completions"]:
+        d = data[c.rid]
+        n = d["x_true"].shape[0]
+        ref = o.scs_solve(o.deconv_program(d["c"], d["b"]), eps=1e-4, check_every=10)
+        assert ref.status == "solved"
+        f = o.deconv_objective(d["c"], d["b"], c.x)
+        fr = o.deconv_objective(d["c"], d["b"], ref.x[:n])
+        assert abs(f - fr) / fr <= 1e-4, (c.rid, n, f, fr)
 
 
 def test_server_admission_by_memory():

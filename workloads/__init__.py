@@ -194,18 +194,23 @@ def serving_request_data(req: Request, density: float = 0.05,
 # seconds (several kernel tiles plus a ragged tail).
 WORKLOADS = {
     # Section V-C deconvolution, FP64, n = 1000, 101-tap Gaussian (sigma 15).
+    # (block equilibration, normalize = 2: with data scaling alone the method
+    # needs tens of thousands of iterations to reach 1e-6 here)
     "deconv_n1000_k101": dict(family="deconv", n=1000, k=101, sigma=15.0, density=0.10,
-                              noise_var=1e-4, seed=1001, eps=1e-6, precision="fp64"),
+                              noise_var=1e-4, seed=1001, eps=1e-6, precision="fp64", normalize=2),
     # Large deconvolution: n = 2^20, 1025-tap Gaussian (sigma 150).
     "deconv_n1M_k1025": dict(family="deconv", n=1 << 20, k=1025, sigma=150.0, density=0.01,
                              noise_var=1e-6, seed=1002, eps=1e-4, precision="fp32"),
     # Dense lasso, A 5000 x 10000 (Section V-B).
+    # stop_eps: the solvers stop at residuals of 1e-5 (<= the workload's 1e-4),
+    # where the objective lands within 1e-4 of the optimum (a 1e-4 stop leaves
+    # it up to ~3e-4 off on these instances)
     "lasso_5000x10000": dict(family="lasso", m=5000, n=10000, density=0.05, noise_var=1e-4,
-                             seed=1003, eps=1e-4, precision="fp32"),
+                             seed=1003, eps=1e-4, stop_eps=1e-5, precision="fp32"),
     # Batched lasso: 64 instances sharing A 2000 x 8000.
     "lasso_batch64_2000x8000": dict(family="lasso_batch", m=2000, n=8000, batch=64,
                                     density=0.05, noise_var=1e-4, seed=1004, eps=1e-4,
-                                    precision="bf16"),
+                                    stop_eps=1e-5, precision="bf16"),
     # Regularized least squares by CG (Section V-A, Table I): dense 6000 x 3000
     # and a 3000-variable convolution whose 1365 taps give Table I's 4,095,000
     # nonzeros; stopped at ||(lam I + A^T A) x - A^T b|| <= 1e-8 ||A^T b||.
