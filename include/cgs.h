@@ -300,6 +300,31 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
 int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice);
 void cgs_solver_destroy(cgs_solver* s);
 
+/* ---------------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory (a serving loop or a harness
+ * that must not call hipMalloc): one solve of one problem -- cgs_solver_create,
+ * cgs_solver_set_data, cgs_solve and cgs_solver_get_solution in one call -- with
+ * the workspace taken from a fixed array in device memory instead of the
+ * caller's buffer.  Each GPU the library runs on holds one such array of
+ * CGS_NOALLOC_SCRATCH_BYTES from the time the library's code is loaded until
+ * the process ends; the call makes no HIP allocation of any kind (no device,
+ * pinned or graph memory: check intervals run without a graph, use_graph is
+ * ignored) and needs no workspace argument.
+ * Arguments are those of cgs_solver_create (batch 1, st->precision CGS_FP64 or
+ * CGS_FP32) and cgs_solver_set_data; x (n), y (m), sl (m) and info (one entry)
+ * receive the results as in cgs_solver_get_solution and cgs_solve (any may be
+ * NULL).  The stream must belong to the current device.
+ * Errors: CGS_ENOMEM when the problem's workspace (cgs_workspace_bytes) exceeds
+ * CGS_NOALLOC_SCRATCH_BYTES, CGS_EINVAL for CGS_BF16, plus those of the calls
+ * it stands for.  Calls on one device share its array: they run one at a
+ * time (a lock per device; overlapping calls from other host threads wait),
+ * and each call rewrites everything it reads before reading it.  The call
+ * returns after its device work has finished. */
+#define CGS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int cgs_solve_noalloc(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, const cgs_settings* st,
+                      const double* b, const double* c, void* stream, double* x, double* y, double* sl,
+                      cgs_info* info);
+
 /* ---------------------------------------------------------------- server
  * Continuous batching of independent problems, each with its own operator
  * (same block kinds; any sizes), cone and data.  Requests are admitted while a

@@ -7,7 +7,8 @@ workspace and to name the HIP stream.  There is no CPU fallback: importing the
 binding raises if the library is missing.
 """
 from ._lib import (  # noqa: F401
-    CgsError, Settings, Info, Operator, Solver, Server, lib, library_path,
+    CgsError, Settings, Info, Operator, Solver, Server, lib, library_path, solve_noalloc,
+    NOALLOC_SCRATCH_BYTES,
     FP64, FP32, BF16, SOLVED, MAX_ITERS, INFEASIBLE, UNBOUNDED, NUMERICAL, RUNNING,
     STATUS_NAMES,
 )

@@ -99,6 +99,8 @@ _SIGS = {
     "cgs_solver_kernel_time": (C.c_int, [_P, C.c_int32, C.c_int32, _DP]),
     "cgs_solver_autotune": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32)]),
     "cgs_solver_destroy": (None, [_P]),
+    "cgs_solve_noalloc": (C.c_int, [_P, _I64, _I64P, _I64, C.POINTER(Settings), _DP, _DP, _P, _DP, _DP,
+                                    _DP, C.POINTER(Info)]),
     "cgs_server_request_bytes": (C.c_int, [_P, _I64, _I64P, _I64, C.c_int32,
                                            C.POINTER(C.c_size_t)]),
     "cgs_server_create": (C.c_int, [_I64, C.POINTER(Settings), _P, C.c_size_t, _P,
@@ -328,6 +330,24 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20   # CGS_NOALLOC_SCRATCH_BYTES of cgs.h
+
+
+def solve_noalloc(op: Operator, l: int, q: Sequence[int], b, c, settings: Optional[Settings] = None,
+                  stream=None):
+    """One solve through cgs_solve_noalloc (no memory allocated by the library:
+    its workspace is the library's fixed device array).  Returns x, y, s, info."""
+    st = settings if settings is not None else Settings.make()
+    qa, nq = _q(q)
+    b = _f64(b, op.m)
+    c = _f64(c, op.n)
+    x, y, s = np.empty(op.n), np.empty(op.m), np.empty(op.m)
+    info = Info()
+    _check(lib().cgs_solve_noalloc(op._h, int(l), qa.ctypes.data_as(_I64P), nq, C.byref(st), _dp(b), _dp(c),
+                                   _stream_handle(stream), _dp(x), _dp(y), _dp(s), C.byref(info)))
+    return x, y, s, info.as_dict()
 
 
 class Server:

@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libcgs.so")
 
-SOURCES = ["kernels.hip", "gemm.hip", "fused.hip", "conv_mfma.hip", "conv_fft.hip", "engine.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "gemm.hip", "fused.hip", "conv_mfma.hip", "conv_fft.hip", "engine.cpp", "api.cpp",
+           "noalloc.hip"]
 ARCH = os.environ.get("CGS_OFFLOAD_ARCH", "gfx950")
 
 

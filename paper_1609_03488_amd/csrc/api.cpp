@@ -300,6 +300,14 @@ int cgs_workspace_bytes(const cgs_op* op, int64_t l, const int64_t* q, int64_t n
 int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
                       const cgs_settings* st, int64_t batch, void* workspace, size_t ws_bytes,
                       void* stream, cgs_solver** out) {
+    return cgs::solver_create(op, l, q, nq, st, batch, workspace, ws_bytes, stream, false, out);
+}
+
+}  // extern "C"
+
+int cgs::solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, const cgs_settings* st,
+                       int64_t batch, void* workspace, size_t ws_bytes, void* stream, bool pageable,
+                       cgs_solver** out) {
     if (!out) return fail(CGS_EINVAL, "out is null");
     *out = nullptr;
     SolverLayout L;
@@ -316,6 +324,7 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
     e.stream = (hipStream_t)stream;
     e.cg_launch = st->cg_max_iters;
     e.lone = batch == 1 ? 1 : 0;
+    e.pageable = pageable;
     char* p = (char*)workspace;
     e.tab_dev = p; e.tab_cap = L.tab; p += L.tab;
     e.work_dev = p; e.work_cap = L.work; p += L.work;
@@ -355,6 +364,8 @@ int cgs_solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq,
     *out = s.release();
     return CGS_OK;
 }
+
+extern "C" {
 
 int cgs_solver_set_data(cgs_solver* s, int64_t inst, const double* b, const double* c) {
     if (!s) return fail(CGS_EINVAL, "solver is null");

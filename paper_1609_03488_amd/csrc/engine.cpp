@@ -486,9 +486,11 @@ Engine::~Engine() {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (side) (void)hipStreamDestroy(side);
-    if (tab_host) (void)hipHostFree(tab_host);
-    if (scal_host) (void)hipHostFree(scal_host);
-    if (stg.host) (void)hipHostFree(stg.host);
+    if (!pageable) {
+        if (tab_host) (void)hipHostFree(tab_host);
+        if (scal_host) (void)hipHostFree(scal_host);
+        if (stg.host) (void)hipHostFree(stg.host);
+    }
 }
 
 void Engine::drop_graph() {
@@ -522,12 +524,26 @@ void Engine::adapt_cg() {
 }
 
 int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_doubles) {
-    CGS_HIP(hipHostMalloc((void**)&tab_host, std::max<size_t>(tab_bytes, 256), hipHostMallocDefault));
+    const size_t tb = std::max<size_t>(tab_bytes, 256);
+    const size_t sb = std::max<size_t>(1, (size_t)max_inst) * NSC * sizeof(double);
+    const size_t gb = (size_t)stg_doubles * sizeof(double);
+    if (pageable) {
+        const size_t tw = (tb + 7) / 8, sw = sb / 8, gw = gb / 8;
+        try {
+            host_store.assign(tw + sw + gw, 0.0);
+        } catch (...) {
+            return fail(CGS_ENOMEM, "host allocation failed");
+        }
+        tab_host = reinterpret_cast<char*>(host_store.data());
+        scal_host = host_store.data() + tw;
+        stg.host = host_store.data() + tw + sw;
+    } else {
+        CGS_HIP(hipHostMalloc((void**)&tab_host, tb, hipHostMallocDefault));
+        CGS_HIP(hipHostMalloc((void**)&scal_host, sb, hipHostMallocDefault));
+        CGS_HIP(hipHostMalloc((void**)&stg.host, gb, hipHostMallocDefault));
+    }
     tab_host_cap = tab_bytes;
-    CGS_HIP(hipHostMalloc((void**)&scal_host, std::max<size_t>(1, (size_t)max_inst) * NSC * sizeof(double),
-                          hipHostMallocDefault));
     scal_host_cap = max_inst;
-    CGS_HIP(hipHostMalloc((void**)&stg.host, (size_t)stg_doubles * sizeof(double), hipHostMallocDefault));
     stg.cap = stg_doubles;
     return CGS_OK;
 }

@@ -57,6 +57,11 @@ struct cgs_op {
 namespace cgs {
 
 int validate_cone(int64_t m, int64_t l, const int64_t* q, int64_t nq);
+// cgs_solver_create with the choice of host buffers: pageable = true keeps the
+// solver's host-side staging in ordinary host memory (no HIP allocation call)
+int solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, const cgs_settings* st,
+                  int64_t batch, void* workspace, size_t ws_bytes, void* stream, bool pageable,
+                  cgs_solver** out);
 int validate_settings(const cgs_settings* st);
 
 // ---------------------------------------------------------------- staging
@@ -152,9 +157,13 @@ class Engine {
 
     char* tab_dev = nullptr;  size_t tab_cap = 0;
     char* work_dev = nullptr; size_t work_cap = 0;
-    char* tab_host = nullptr; size_t tab_host_cap = 0;   // pinned
-    double* scal_host = nullptr; int scal_host_cap = 0;   // pinned
+    char* tab_host = nullptr; size_t tab_host_cap = 0;   // pinned (pageable: host_store)
+    double* scal_host = nullptr; int scal_host_cap = 0;   // pinned (pageable: host_store)
     Staging stg;
+    // host buffers in ordinary (pageable) host memory instead of pinned memory,
+    // for a solver that must not call any HIP allocation routine
+    bool pageable = false;
+    std::vector<double> host_store;
 
     std::vector<InstRec> recs;
     TableImage im;
