@@ -103,6 +103,7 @@ def run_deconv(args, cfg):
     pr = P.deconv_problem(data["c"], data["b"])
     stream = torch.cuda.Stream()
     prec = P.FP64 if cfg["precision"] == "fp64" else P.FP32
+    tuned = None
     st = P.Settings.make(precision=prec, eps=cfg["eps"], check_every=10, normalize=args.normalize)
     if args.max_iters:
         st.max_iters = args.max_iters
@@ -118,8 +119,9 @@ def run_deconv(args, cfg):
         s.set_data(0, pr.b, pr.c)
         log(f"convolution {ENGINE_NAMES[engine]} (fixed)")
     elif prec == P.FP32 and not args.no_autotune:
-        engine = s.autotune(reps=10)["conv_mfma"]
-        log(f"autotune: convolution {ENGINE_NAMES[engine]}")
+        tuned = s.autotune(reps=10)
+        engine = tuned["conv_mfma"]
+        log(f"autotune: convolution {ENGINE_NAMES[engine]}, vector tiles of {tuned['vec_tile']}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
     last = infos[-1][0]
     t_fwd = s.kernel_time(0, 20)
@@ -193,7 +195,7 @@ def run_deconv(args, cfg):
     out.update({
         "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed,
-        "status": last["status_name"], "max_iters_cap": args.max_iters,
+        "status": last["status_name"], "max_iters_cap": args.max_iters, "autotune": tuned,
         "roofline": conv_roofline(engine, prec == P.FP32, n, k, t_fwd, t_adj),
         "conv_direct_sum_equivalent_tflops": achieved,
         "cpu_baseline": cpu, "verify": verify,
@@ -276,6 +278,10 @@ def run_lasso(args, cfg):
         st.max_iters = args.max_iters
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
     s.set_data(0, pr.b, pr.c)
+    tuned = None
+    if not args.no_autotune:
+        tuned = s.autotune(reps=5)
+        log(f"autotune: vector tiles of {tuned['vec_tile']}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
     last = infos[-1][0]
     t_a, t_at = s.kernel_time(2, 20), s.kernel_time(3, 20)
@@ -309,6 +315,7 @@ def run_lasso(args, cfg):
     out.update({
         "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed, "status": last["status_name"],
+        "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "kernel": "k_gemv<float> (A and A^T, FP32, 200 MB each; fits the 256 MB MALL)",
@@ -417,9 +424,11 @@ def run_lasso_conv(args, cfg):
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
     s.set_data(0, pr.b, pr.c)
     engine = 1
+    tuned = None
     if not args.no_autotune:
-        engine = s.autotune(reps=10)["conv_mfma"]
-        log(f"autotune: convolution {ENGINE_NAMES[engine]}")
+        tuned = s.autotune(reps=10)
+        engine = tuned["conv_mfma"]
+        log(f"autotune: convolution {ENGINE_NAMES[engine]}, vector tiles of {tuned['vec_tile']}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
     last = infos[-1][0]
     t_a, t_at = s.kernel_time(0, 20), s.kernel_time(1, 20)
@@ -452,7 +461,7 @@ def run_lasso_conv(args, cfg):
     out.update({
         "time_to_eps_s": elapsed / args.steps, "admm_iters": last["iters"], "cg_iters": last["cg_iters"],
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed, "status": last["status_name"],
-        "roofline": roof,
+        "autotune": tuned, "roofline": roof,
         "cpu_baseline": cpu, "verify": verify,
     })
     return out
@@ -478,8 +487,9 @@ def run_lasso_batch(args, cfg):
         s.set_data(i, pr.b, pr.c)
     tuned = None
     if not args.no_autotune:
-        tuned = s.autotune(reps=10)["gemm_target_wgs"]
-        log(f"autotune: batched GEMM aims at {tuned} workgroups")
+        tuned = s.autotune(reps=5)
+        log(f"autotune: batched GEMM aims at {tuned['gemm_target_wgs']} workgroups, "
+            f"vector tiles of {tuned['vec_tile']}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])
     last = infos[-1]
     solves = B * args.steps
@@ -541,7 +551,7 @@ def run_lasso_batch(args, cfg):
                        "stop_eps": stop_eps, "normalize": args.normalize,
                        "products": "bf16 MFMA, fp32 accumulation; refinement phase bf16 hi/lo; "
                                    "final test (and iterations where it fails) on the fp32 operator",
-                       "gemm_target_wgs": tuned,
+                       "autotune": tuned,
                        "scalars": "f64"})
     out.update({
         "time_per_batch_s": elapsed / args.steps,

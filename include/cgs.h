@@ -153,7 +153,10 @@ typedef struct {
                               fused_lone_max): alone, one workgroup races the whole
                               chip, and measured per-step times cross near n + m =
                               8000 (default 8192; 0: fused_max alone decides)       */
-    int32_t reserved[2];
+    int32_t vec_tile;      /* elements per vector tile of the vector kernels and their
+                              reductions: 1024 or 2048 (0, the default: 2048; the
+                              autotuner may change it)                              */
+    int32_t reserved[1];
 } cgs_settings;
 
 /* Per-instance result. */
@@ -290,13 +293,19 @@ int cgs_solver_normal_solve(cgs_solver* s, const double* rhs, const double* z0, 
  * application p + A^T A p.  *avg_ms receives the mean time per launch (per
  * operator block, for 0-3); CGS_ENOTFOUND if the operator has no such block. */
 int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* avg_ms);
-/* Autotuner: times the candidate kernel configurations on the solver's own
- * operator and vectors (HIP events, `reps` launches each) and keeps the
- * fastest -- the convolution engine for FP32 (vector ALU, matrix cores, or FFT
- * when the kernels are short enough) and the split-K width of the batched BF16
- * GEMM.  choice[2] (nullable) receives {conv_mfma (or -1), GEMM workgroup
- * target (or -1)}.  Only how the same products are computed changes: results
- * agree to the products' rounding. */
+/* Autotuner: picks, for this solver's own operator and instances, the FP32
+ * convolution engine (vector ALU, matrix cores, or FFT when the kernels are
+ * short enough), the split-K width of the batched BF16 GEMM and the length of
+ * the vector tiles (1024 or 2048 elements) the vector kernels and reductions
+ * work on.  With data on every instance it times each combination on whole
+ * ADMM steps of the instances (setup, three untimed steps, then `reps` steps
+ * between HIP events: the launches the solve runs, folded ones included) and
+ * restarts every instance from u = v = (0, 0, 1) afterwards; without data it
+ * times the operator's launches alone (vector tiles unchanged).  choice[4]
+ * (nullable) receives {conv engine (conv_mfma value, or -1), GEMM workgroup
+ * target (or -1), vector tile length, -1}.  Only how the same products and
+ * sums are computed changes: applies agree to their rounding, and reductions
+ * keep a fixed order for each choice. */
 int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice);
 void cgs_solver_destroy(cgs_solver* s);
 

@@ -32,7 +32,7 @@ class Settings(C.Structure):
         ("setup_tol", C.c_double), ("setup_max_iters", C.c_int32), ("use_graph", C.c_int32),
         ("bf16_phase1_digits", C.c_int32), ("cg_adaptive", C.c_int32),
         ("fused_max", C.c_int32), ("conv_mfma", C.c_int32), ("normalize", C.c_int32),
-        ("fused_lone_max", C.c_int32), ("reserved", C.c_int32 * 2),
+        ("fused_lone_max", C.c_int32), ("vec_tile", C.c_int32), ("reserved", C.c_int32 * 1),
     ]
 
     @classmethod
@@ -262,10 +262,12 @@ class Solver:
         return float(ms.value)
 
     def autotune(self, reps: int = 10) -> dict:
-        """Pick the fastest convolution engine / GEMM split for this operator."""
-        ch = (C.c_int32 * 2)()
+        """Pick the fastest convolution engine, GEMM split and vector tile for
+        this solver (timed on whole ADMM steps when every instance has data;
+        the instances restart afterwards)."""
+        ch = (C.c_int32 * 4)()
         _check(lib().cgs_solver_autotune(self._h, int(reps), ch))
-        return {"conv_mfma": int(ch[0]), "gemm_target_wgs": int(ch[1])}
+        return {"conv_mfma": int(ch[0]), "gemm_target_wgs": int(ch[1]), "vec_tile": int(ch[2])}
 
     def solve(self) -> List[dict]:
         infos = (Info * self.batch)()

@@ -59,7 +59,7 @@ int solver_layout(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq, con
         r.op = &shape;
     }
     cgs::TableImage im;
-    cgs::build_image(recs, st->precision, im);
+    cgs::build_image(recs, st->precision, im, cgs::VEC_TILE_MIN);   // (the most tiles a tuning can ask for)
     L->tab = cgs::align256(cgs::image_table_bytes(im));
     L->work = cgs::align256(cgs::image_work_bytes(im));
     L->stg_doubles = cgs::staging_doubles(*op, std::max(op->n, op->m));
@@ -323,6 +323,7 @@ int cgs::solver_create(const cgs_op* op, int64_t l, const int64_t* q, int64_t nq
     e.st = *st;
     e.stream = (hipStream_t)stream;
     e.cg_launch = st->cg_max_iters;
+    e.vec_tile = st->vec_tile ? st->vec_tile : cgs::VEC_TILE;
     e.lone = batch == 1 ? 1 : 0;
     e.pageable = pageable;
     char* p = (char*)workspace;
@@ -442,55 +443,149 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
     return CGS_OK;
 }
 
+static int run_setup_if_needed(cgs_solver* s, bool* did);
+
+// Every instance back to u = v = (0, 0, 1) with its data kept; instances
+// without data stay inactive (cgs_solver_reset).
+static int restart_all(cgs_solver* s) {
+    cgs::Engine& e = s->eng;
+    CGS_TRY(e.reset(-1));
+    for (int64_t i = 0; i < s->batch; ++i)
+        if (!s->has_data[(size_t)i]) CGS_TRY(e.set_scalar((int)i, cgs::SC_ACTIVE, 0.0));
+    CGS_HIP(hipStreamSynchronize(e.stream));
+    return CGS_OK;
+}
+
+// Device time of one ADMM step of every instance with the current kernel
+// choices, from a fresh start: setup, three untimed steps, then `reps` steps
+// between HIP events (one CG launch per step, the count the solve settles on
+// once its first steps are past); the instances restart afterwards.
+static int time_steps(cgs_solver* s, int reps, double* ms_per_step) {
+    cgs::Engine& e = s->eng;
+    CGS_TRY(restart_all(s));
+    CGS_TRY(run_setup_if_needed(s, nullptr));
+    e.refresh();
+    const int keep = e.cg_launch;
+    e.cg_launch = 1;
+    for (int i = 0; i < 3; ++i) e.admm_step();
+    hipEvent_t a, b;
+    CGS_HIP(hipEventCreate(&a));
+    CGS_HIP(hipEventCreate(&b));
+    CGS_HIP(hipEventRecord(a, e.stream));
+    for (int i = 0; i < reps; ++i) e.admm_step();
+    CGS_HIP(hipEventRecord(b, e.stream));
+    CGS_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    CGS_HIP(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    e.cg_launch = keep;
+    CGS_HIP(hipGetLastError());
+    *ms_per_step = (double)ms / reps;
+    return restart_all(s);
+}
+
 int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice) {
     if (!s) return fail(CGS_EINVAL, "solver is null");
     if (reps < 1) return fail(CGS_EINVAL, "reps must be >= 1");
     cgs::Engine& e = s->eng;
-    int32_t out[2] = {-1, -1};
-    double best = 0.0;
+    bool have_data = true;
+    for (int64_t i = 0; i < s->batch; ++i) have_data = have_data && s->has_data[(size_t)i];
+    bool fft = false;
+    for (const auto& c : e.cf) fft = fft || c.fft;
+    std::vector<int> engines, tiles, targets;
     if (!e.cf.empty() && e.prec == 1) {
-        // convolution engine: vector ALU, matrix cores or FFT, A and A^T together
-        bool fft = false;
-        for (const auto& c : e.cf) fft = fft || c.fft;
-        double t[3] = {0.0, 0.0, 0.0};
-        int bestm = 0;
-        for (int m = 0; m < (fft ? 3 : 2); ++m) {
-            e.st.conv_mfma = m;
-            double a = 0.0, b = 0.0;
-            // untimed first launches: the runtime loads a kernel's code on its
-            // first launch, which the events would otherwise count
-            CGS_TRY(cgs_solver_kernel_time(s, 0, 1, &a));
-            CGS_TRY(cgs_solver_kernel_time(s, 1, 1, &b));
-            CGS_TRY(cgs_solver_kernel_time(s, 0, reps, &a));
-            CGS_TRY(cgs_solver_kernel_time(s, 1, reps, &b));
-            t[m] = a + b;
-            if (t[m] < t[bestm]) bestm = m;
-        }
-        e.st.conv_mfma = bestm;
-        out[0] = e.st.conv_mfma;
+        engines = {0, 1};
+        if (fft) engines.push_back(2);
+    } else {
+        engines = {e.st.conv_mfma};
     }
     if (e.use_gemm) {
-        // split-K of the batched GEMM: workgroups aimed for
-        int bt = e.gemm_target;
-        for (int target = 128; target <= cgs::GEMM_TARGET_MAX; target *= 2) {
-            e.gemm_target = target;
-            double a = 0.0, b = 0.0;
-            CGS_TRY(cgs_solver_kernel_time(s, 2, 1, &a));
-            CGS_TRY(cgs_solver_kernel_time(s, 3, 1, &b));
-            CGS_TRY(cgs_solver_kernel_time(s, 2, reps, &a));
-            CGS_TRY(cgs_solver_kernel_time(s, 3, reps, &b));
-            if (target == 128 || a + b < best) {
-                best = a + b;
-                bt = target;
+        for (int t = 128; t <= cgs::GEMM_TARGET_MAX; t *= 2) targets.push_back(t);
+    } else {
+        targets = {e.gemm_target};
+    }
+    // vector tiles only matter on the one-launch-per-kernel path
+    if (have_data && e.n_multi > 0) tiles = {cgs::VEC_TILE_MIN, cgs::VEC_TILE};
+    else tiles = {e.vec_tile};
+    int best_m = e.st.conv_mfma, best_t = e.gemm_target, best_v = e.vec_tile;
+    if (have_data && e.n_multi > 0) {
+        // every combination timed on whole ADMM steps of the solver's own
+        // instances: the launches the solve runs, folded ones included
+        double best = 0.0;
+        bool first = true;
+        for (int v : tiles) {
+            if (v != e.vec_tile) {
+                e.vec_tile = v;
+                CGS_TRY(e.build(e.recs));
+            }
+            for (int m : engines) {
+                for (int t : targets) {
+                    e.st.conv_mfma = m;
+                    e.gemm_target = t;
+                    double ms = 0.0;
+                    CGS_TRY(time_steps(s, reps, &ms));
+                    if (first || ms < best) {
+                        best = ms;
+                        best_m = m;
+                        best_t = t;
+                        best_v = v;
+                        first = false;
+                    }
+                }
             }
         }
-        e.gemm_target = bt;
-        out[1] = bt;
+        e.st.conv_mfma = best_m;
+        e.gemm_target = best_t;
+        if (best_v != e.vec_tile) {
+            e.vec_tile = best_v;
+            CGS_TRY(e.build(e.recs));
+        }
+        CGS_TRY(restart_all(s));
+    } else {
+        // no data yet (or every instance on the fused path): the operator's
+        // launches alone, A and A^T
+        if (engines.size() > 1) {
+            double best = 0.0;
+            for (int m : engines) {
+                e.st.conv_mfma = m;
+                double a = 0.0, b = 0.0;
+                // untimed first launches: the runtime loads a kernel's code on its
+                // first launch, which the events would otherwise count
+                CGS_TRY(cgs_solver_kernel_time(s, 0, 1, &a));
+                CGS_TRY(cgs_solver_kernel_time(s, 1, 1, &b));
+                CGS_TRY(cgs_solver_kernel_time(s, 0, reps, &a));
+                CGS_TRY(cgs_solver_kernel_time(s, 1, reps, &b));
+                if (m == engines[0] || a + b < best) {
+                    best = a + b;
+                    best_m = m;
+                }
+            }
+            e.st.conv_mfma = best_m;
+        }
+        if (e.use_gemm) {
+            double best = 0.0;
+            for (int target : targets) {
+                e.gemm_target = target;
+                double a = 0.0, b = 0.0;
+                CGS_TRY(cgs_solver_kernel_time(s, 2, 1, &a));
+                CGS_TRY(cgs_solver_kernel_time(s, 3, 1, &b));
+                CGS_TRY(cgs_solver_kernel_time(s, 2, reps, &a));
+                CGS_TRY(cgs_solver_kernel_time(s, 3, reps, &b));
+                if (target == targets[0] || a + b < best) {
+                    best = a + b;
+                    best_t = target;
+                }
+            }
+            e.gemm_target = best_t;
+        }
     }
     e.drop_graph();
     if (choice) {
-        choice[0] = out[0];
-        choice[1] = out[1];
+        choice[0] = (!e.cf.empty() && e.prec == 1) ? e.st.conv_mfma : -1;
+        choice[1] = e.use_gemm ? e.gemm_target : -1;
+        choice[2] = e.vec_tile;
+        choice[3] = -1;
     }
     return CGS_OK;
 }

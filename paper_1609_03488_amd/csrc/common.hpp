@@ -210,7 +210,8 @@ struct Tables {
     int nx_tiles, ny_tiles, nseg, ninst;
 };
 
-constexpr int VEC_TILE = 2048;     // elements per X/Y tile
+constexpr int VEC_TILE = 2048;     // most elements per X/Y tile (the kernels' per-thread share)
+constexpr int VEC_TILE_MIN = 1024; // smallest tile length the autotuner tries (sizes the tables)
 constexpr int VEC_NT = 256;        // threads per vector-kernel block
 constexpr int CONV_TILE_F32 = 512;   // outputs per convolution tile (64 lanes x 8)
 constexpr int CONV_TILE_F64 = 256;   // (64 lanes x 4)

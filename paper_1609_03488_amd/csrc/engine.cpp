@@ -54,6 +54,8 @@ int validate_settings(const cgs_settings* s) {
     if (s->normalize < 0 || s->normalize > 2) return fail(CGS_EINVAL, "normalize must be 0, 1 or 2");
     if (s->fused_max < 0 || s->fused_lone_max < 0) return fail(CGS_EINVAL, "fused_max, fused_lone_max must be >= 0");
     if (s->conv_mfma < 0 || s->conv_mfma > 2) return fail(CGS_EINVAL, "conv_mfma must be 0, 1 or 2");
+    if (s->vec_tile != 0 && s->vec_tile != VEC_TILE_MIN && s->vec_tile != VEC_TILE)
+        return fail(CGS_EINVAL, "vec_tile must be 0, %d or %d", VEC_TILE_MIN, VEC_TILE);
     return CGS_OK;
 }
 
@@ -369,7 +371,7 @@ int download_f64(const Staging& stg, hipStream_t st, int prec, const void* src, 
 }
 
 // ---------------------------------------------------------------- tables
-void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im) {
+void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im, int vec_tile) {
     im = TableImage{};
     const int64_t ct = conv_tile(precision);
     for (size_t i = 0; i < recs.size(); ++i) {
@@ -383,12 +385,12 @@ void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im
         d.nys = round_up(r.m, XY_ALIGN);
         d.l = r.l;
         d.xt0 = (int32_t)im.xt.size();
-        for (int64_t s = 0; s < r.n; s += VEC_TILE)
-            im.xt.push_back(VecTile{ii, -1, s, (int32_t)std::min<int64_t>(VEC_TILE, r.n - s), 0});
+        for (int64_t s = 0; s < r.n; s += vec_tile)
+            im.xt.push_back(VecTile{ii, -1, s, (int32_t)std::min<int64_t>(vec_tile, r.n - s), 0});
         d.xt1 = (int32_t)im.xt.size();
         d.yt0 = (int32_t)im.yt.size();
-        for (int64_t s = 0; s < r.l; s += VEC_TILE)
-            im.yt.push_back(VecTile{ii, -1, s, (int32_t)std::min<int64_t>(VEC_TILE, r.l - s), 0});
+        for (int64_t s = 0; s < r.l; s += vec_tile)
+            im.yt.push_back(VecTile{ii, -1, s, (int32_t)std::min<int64_t>(vec_tile, r.l - s), 0});
         d.sg0 = (int32_t)im.seg.size();
         int64_t off = r.l;
         for (int64_t qj : r.q) {
@@ -401,7 +403,7 @@ void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im
             // a tile spans at most VEC_TILE elements of the 4-element grid
             // (vector kernels walk tiles in aligned chunks of four)
             for (int64_t s = 0; s < qj;) {
-                const int64_t len = std::min<int64_t>(VEC_TILE - ((off + s) & 3), qj - s);
+                const int64_t len = std::min<int64_t>(vec_tile - ((off + s) & 3), qj - s);
                 im.yt.push_back(VecTile{ii, sid, off + s, (int32_t)len, 0});
                 s += len;
             }
@@ -551,7 +553,7 @@ int Engine::init_host_buffers(size_t tab_bytes, int max_inst, int64_t stg_double
 int Engine::build(const std::vector<InstRec>& r) {
     recs = r;
     rounds_since_build = 0;
-    build_image(recs, precision, im);
+    build_image(recs, precision, im, vec_tile);
     // each instance's path depends on its own size only (never on the mix);
     // a solver's single instance has the whole chip to itself on the other path
     n_fused = n_multi = 0;

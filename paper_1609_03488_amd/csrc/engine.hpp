@@ -140,7 +140,8 @@ struct TableImage {
     std::vector<DenseBlock> dblk;
     std::vector<std::vector<DenseTile>> dfwd, dadj;  // per dense slot
 };
-void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im);
+// vec_tile: elements per X/Y vector tile, VEC_TILE_MIN..VEC_TILE
+void build_image(const std::vector<InstRec>& recs, int precision, TableImage& im, int vec_tile = VEC_TILE);
 size_t image_table_bytes(const TableImage& im);
 size_t image_work_bytes(const TableImage& im);
 // dense entries above which an instance never takes the fused path (a dense
@@ -198,6 +199,7 @@ class Engine {
     size_t panel_stride = 0;
     float* gemm_part = nullptr;
     int gemm_target = 512;       // GEMM workgroups aimed for (autotuned)
+    int vec_tile = VEC_TILE;     // elements per X/Y vector tile (autotuned)
 
     // side stream for the fused launch, overlapped with the one-launch-per-kernel
     // round of the other instances (disjoint memory); default priority

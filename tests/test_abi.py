@@ -82,6 +82,8 @@ def test_workspace_and_cone_validation():
     assert _ws(op, 5, [5], eps=0.0)[0] == -1
     assert _ws(op, 5, [5], alpha=2.0)[0] == -1
     assert _ws(op, 5, [5], precision=7)[0] == -1
+    assert _ws(op, 5, [5], vec_tile=1024)[0] == 0
+    assert _ws(op, 5, [5], vec_tile=512)[0] == -1    # tiles of 1024 or 2048 only
     # more batch instances need more memory
     rc1, nb1 = _ws(op, 10, [])
     assert rc1 == 0

@@ -633,6 +633,51 @@ def test_autotune_keeps_results_within_bounds():
                   <= tol * _abs_bound(progs[0], y, True) + 1e-30)
 
 
+@pytest.mark.parametrize("vec_tile", [1024, 2048])
+@pytest.mark.parametrize("idx,prec,eps", [(0, P.FP32, 1e-4), (1, P.FP64, 1e-6), (2, P.FP32, 1e-4)])
+def test_vector_tiles_solve_matches_oracle(idx, prec, eps, vec_tile):
+    """Either vector tile length the autotuner chooses from gives a solution
+    whose objective is within 1e-4 of the oracle's at the same eps (the tiles
+    change only how the vector kernels and reductions split the work)."""
+    name, pr, prog = ITER_CASES[idx]
+    _say("vector tiles", name, prec, vec_tile)
+    s = _solver(pr, prec, eps=eps, check_every=10, fused_max=0, vec_tile=vec_tile)
+    s.set_data(0, pr.b, pr.c)
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, y, sl = s.solution(0)
+    rp, rd, gap, _, _ = o.scs.residuals(prog, x, y, 1.0, sl)
+    assert max(rp, rd, gap) <= 1.05 * eps, (rp, rd, gap)
+    ref = o.scs_solve(prog, eps=eps, check_every=10)
+    if prog.family in ("deconv", "lasso", "lasso_conv"):
+        f, fr = _objective(prog, x), _objective(prog, ref.x)
+    else:   # a generic program: its conic objective c^T x
+        f, fr = float(prog.c @ x), float(prog.c @ ref.x)
+    assert abs(f - fr) <= 1e-4 * max(1.0, abs(fr)), (f, fr)
+
+
+def test_autotune_on_steps_then_solve():
+    """With data on the instance the autotuner times whole ADMM steps for each
+    engine and tile length, then restarts the instance: the following solve
+    starts from u = v = (0, 0, 1) and matches the oracle."""
+    import torch
+    name, pr, prog = CASES[1]
+    _say("autotune on steps", name)
+    s = P.Solver(pr.op, pr.l, pr.q, P.Settings.make(precision=P.FP32, eps=1e-4, fused_max=0),
+                 stream=torch.cuda.Stream())
+    s.set_data(0, pr.b, pr.c)
+    ch = s.autotune(reps=3)
+    assert ch["conv_mfma"] in (0, 1, 2) and ch["vec_tile"] in (1024, 2048) and ch["gemm_target_wgs"] == -1
+    ux, uy, tau, vs, kappa = s.state(0)
+    assert tau == 1.0 and kappa == 1.0 and not ux.any() and not uy.any() and not vs.any()
+    info = s.solve()[0]
+    assert info["status"] == P.SOLVED, info
+    x, _, _ = s.solution(0)
+    ref = o.scs_solve(prog, eps=1e-4, check_every=10)
+    f, fr = _objective(prog, x), _objective(prog, ref.x)
+    assert abs(f - fr) / abs(fr) <= 1e-4, (f, fr)
+
+
 @pytest.mark.parametrize("fused", [0, 65536], ids=["multikernel", "fused"])
 @pytest.mark.parametrize("idx,prec,eps", [(0, P.FP32, 1e-4), (1, P.FP64, 1e-6)])
 def test_solve_with_block_equilibration_matches_oracle(idx, prec, eps, fused):
