@@ -95,8 +95,10 @@ typedef struct {
     int32_t cg_max_iters;  /* CG iterations per ADMM step, upper bound (>= 1)         */
     double cg_tol;         /* CG stops when ||r|| <= ||rhs|| * max(cg_floor,          */
     double cg_rate;        /*        cg_tol / (k+1)^cg_rate)  at ADMM step k          */
-    double cg_floor;
-    double setup_tol;      /* relative CG tolerance of the embedding-vector solve     */
+    double cg_floor;       /* (CGS_FP64 uses min(cg_floor, eps / 100): its subspace
+                              solves stay well below the target tolerance)          */
+    double setup_tol;      /* relative CG tolerance of the embedding-vector solve
+                              (CGS_FP64 uses min(setup_tol, 1e-10))                  */
     int32_t setup_max_iters; /* CG iteration limit of that solve                      */
     int32_t use_graph;     /* 1: replay each block of check_every steps as a hipGraph */
     int32_t bf16_phase1_digits; /* CGS_BF16: the BF16-product phase solves to

@@ -765,7 +765,7 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         c.part = T.cpart;
         conv(c, 1, XQ, YT, XP, 1.0, G_ADMM);
         launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
-                         CgStart{st.cg_tol, st.cg_rate, st.cg_floor, 1, 1, 1, st.alpha});
+                         CgStart{st.cg_tol, st.cg_rate, cg_floor(), 1, 1, 1, st.alpha});
         return;
     }
     apply(0, YT, XP, -1, 1.0, gate);
@@ -812,7 +812,7 @@ void Engine::admm_step() {
             cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == nl - 1, i == 0);
     } else {
         apply(1, XH, YW, XU, -1.0, G_ADMM);                      // h = u_x - A^T w_y
-        launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, st.cg_floor,
+        launch_cg_init(prec, T, XZ, XR, XP, XK, XH, 1, st.cg_tol, st.cg_rate, cg_floor(),
                        st.cg_max_iters, G_ADMM, stream);         // r = h - K z
         for (int i = 0; i < cg_launch; ++i)
             cg_iter(XZ, G_ADMM_CG, st.cg_max_iters, 1, i, spec_now && i == cg_launch - 1);
@@ -862,7 +862,7 @@ void Engine::fused_steps(int nsteps, int check) {
     fa.eps = st.eps;
     fa.zeta = st.cg_tol;
     fa.rate = st.cg_rate;
-    fa.floor_ = st.cg_floor;
+    fa.floor_ = cg_floor();
     fa.cg_max = st.cg_max_iters;
     fa.max_iters = st.max_iters;
     fa.kc = fused_kc;
@@ -992,7 +992,7 @@ int Engine::setup() {
     // embedding vector when a refined operator restarts the setup)
     apply(0, YT, XG, -1, 1.0, G_SETUP);                           // A g_x
     apply(1, XQ, YT, XG, 1.0, G_SETUP);                           // (I + A^T A) g_x
-    launch_cg_init(prec, T, XG, XR, XP, XQ, XH, 1, 0.0, 0.0, st.setup_tol, st.setup_max_iters,
+    launch_cg_init(prec, T, XG, XR, XP, XQ, XH, 1, 0.0, 0.0, setup_tol(), st.setup_max_iters,
                    G_SETUP, stream);
     int it = 0;
     while (it < st.setup_max_iters) {

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdint>
@@ -234,6 +235,13 @@ class Engine {
     void cg_iter(int z, int gate, int cg_max, int track, int it, int last = 0, int start = 0);
     // CG steps run folded into the A^T launch (FFT engine chosen and the tables allow it)
     bool folded_cg() const { return fold_cg && prec == 1 && st.conv_mfma == 2 && !ca.empty() && ca[0].fft; }
+    // relative floor of the ADMM steps' CG tolerance: cg_floor, and in FP64 at
+    // most eps / 100 (subspace solves well below the target tolerance; FP32
+    // CG cannot go much below its default 1e-6)
+    double cg_floor() const { return precision == CGS_FP64 ? std::min(st.cg_floor, 1e-2 * st.eps) : st.cg_floor; }
+    // relative tolerance of the embedding-vector solve: setup_tol, and in FP64
+    // at most 1e-10 (in FP32 the vector g itself carries about 7 digits)
+    double setup_tol() const { return precision == CGS_FP64 ? std::min(st.setup_tol, 1e-10) : st.setup_tol; }
     void admm_step();
     void fused_steps(int nsteps, int check);
     void check(int gate = G_CHECK);
