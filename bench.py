@@ -317,7 +317,8 @@ def run_lasso(args, cfg):
         "cg_matvecs_per_s": sum(i[0]["cg_iters"] for i in infos) / elapsed, "status": last["status_name"],
         "autotune": tuned,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic("k_gemv"),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": "k_gemv<float> (A and A^T, FP32, 200 MB each; fits the 256 MB MALL)",
                      "bytes_per_launch": bytes_a, "launch_us": {"A": t_a * 1e3, "AT": t_at * 1e3}},
         "cpu_baseline": cpu, "verify": verify,
@@ -559,12 +560,18 @@ def run_lasso_batch(args, cfg):
         "plain_fp32_one_at_a_time_solves_per_s": plain,
         "speedup_vs_plain": (solves / elapsed) / plain if plain > 0 else None,
         "dense_apply_us": {"A": gem[0] * 1e3, "AT": gem[1] * 1e3},
-        "roofline": {"bound": "hbm", "achieved": (2 * m * n * 2 * 2) / ((gem[0] + gem[1]) * 1e-3) / 1e9,
+        # algorithmic bytes of one apply in the BF16 phase: the BF16 matrix W_hi
+        # (2 m n bytes), read once; the launch time covers pack + GEMM + reduce
+        "roofline": {"bound": "hbm", "achieved": (2 * (2 * m * n)) / ((gem[0] + gem[1]) * 1e-3) / 1e9,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": (2 * m * n * 2 * 2) / ((gem[0] + gem[1]) * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                     "traffic": None,
+                     "frac": (2 * (2 * m * n)) / ((gem[0] + gem[1]) * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "traffic": measured_traffic("k_gemm_bf16"),
+                     "traffic_unit": "HBM bytes per k_gemm_bf16 launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
                      "kernel": "pack + k_gemm_bf16 + reduce (A and A^T as BF16 MFMA GEMMs over the batch)",
-                     "bytes_per_launch": 2 * m * n * 2},
+                     "bytes_per_launch": 2 * m * n,
+                     # three BF16 product terms (the input carried to FP32 accuracy) per apply
+                     "mfma_tflops": (2 * 3 * 2 * m * n * B) / ((gem[0] + gem[1]) * 1e-3) / 1e12},
         "cpu_baseline": cpu, "verify": verify,
     })
     return out
