@@ -158,7 +158,14 @@ typedef struct {
     int32_t vec_tile;      /* elements per vector tile of the vector kernels and their
                               reductions: 1024 or 2048 (0, the default: 2048; the
                               autotuner may change it)                              */
-    int32_t reserved[1];
+    int32_t intervals_per_sync; /* check intervals enqueued (one graph) between two
+                              reads of the instances' scalars by the host (>= 1,
+                              default 2).  The termination test still runs every
+                              check_every steps on the device and an instance that
+                              passes it stops there; only the host's decisions
+                              (CG launches per step, a rerun, the end of the solve)
+                              wait for the end of the batch of intervals.  Results
+                              do not depend on it.  A server always uses 1.         */
 } cgs_settings;
 
 /* Per-instance result. */

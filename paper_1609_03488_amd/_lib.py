@@ -32,7 +32,7 @@ class Settings(C.Structure):
         ("setup_tol", C.c_double), ("setup_max_iters", C.c_int32), ("use_graph", C.c_int32),
         ("bf16_phase1_digits", C.c_int32), ("cg_adaptive", C.c_int32),
         ("fused_max", C.c_int32), ("conv_mfma", C.c_int32), ("normalize", C.c_int32),
-        ("fused_lone_max", C.c_int32), ("vec_tile", C.c_int32), ("reserved", C.c_int32 * 1),
+        ("fused_lone_max", C.c_int32), ("vec_tile", C.c_int32), ("intervals_per_sync", C.c_int32),
     ]
 
     @classmethod

@@ -259,6 +259,7 @@ void cgs_settings_default(cgs_settings* st) {
     st->fused_lone_max = 8192;
     st->conv_mfma = 1;
     st->normalize = 1;
+    st->intervals_per_sync = 2;
 }
 
 // Equilibrated data of one instance written into its region (layout of
@@ -730,7 +731,7 @@ static int solve_rounds(cgs_solver* s) {
         }
         if (!any) break;
         const int64_t rem = (int64_t)e.st.max_iters - (int64_t)min_it;
-        const int nsteps = (int)std::max<int64_t>(1, std::min<int64_t>(e.st.check_every, rem));
+        const int nsteps = (int)std::max<int64_t>(1, std::min<int64_t>(e.round_steps(), rem));
         e.adapt_cg();
         CGS_TRY(e.round(nsteps));
     }
@@ -912,6 +913,7 @@ int cgs_server_create(int64_t max_slots, const cgs_settings* st, void* workspace
     e.st = *st;
     e.stream = (hipStream_t)stream;
     e.st.cg_adaptive = 0;     // results must not depend on the other requests in the mix
+    e.st.intervals_per_sync = 1;   // requests arrive and leave at every check
     e.cg_launch = st->cg_max_iters;
     // tables and reduction scratch: a fixed slice of the workspace
     const size_t tab = cgs::align256(std::max<size_t>(size_t(1) << 20, ws_bytes / 64));

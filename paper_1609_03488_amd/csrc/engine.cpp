@@ -54,6 +54,8 @@ int validate_settings(const cgs_settings* s) {
     if (s->normalize < 0 || s->normalize > 2) return fail(CGS_EINVAL, "normalize must be 0, 1 or 2");
     if (s->fused_max < 0 || s->fused_lone_max < 0) return fail(CGS_EINVAL, "fused_max, fused_lone_max must be >= 0");
     if (s->conv_mfma < 0 || s->conv_mfma > 2) return fail(CGS_EINVAL, "conv_mfma must be 0, 1 or 2");
+    if (s->intervals_per_sync < 1 || s->intervals_per_sync > 64)
+        return fail(CGS_EINVAL, "intervals_per_sync must be in [1, 64]");
     if (s->vec_tile != 0 && s->vec_tile != VEC_TILE_MIN && s->vec_tile != VEC_TILE)
         return fail(CGS_EINVAL, "vec_tile must be 0, %d or %d", VEC_TILE_MIN, VEC_TILE);
     return CGS_OK;
@@ -869,6 +871,13 @@ void Engine::fused_steps(int nsteps, int check) {
     launch_fused(prec, T, fa, stream);
 }
 
+void Engine::steps_with_checks(int nsteps) {
+    for (int i = 0; i < nsteps; ++i) {
+        admm_step();
+        if ((i + 1) % st.check_every == 0 || i + 1 == nsteps) check();
+    }
+}
+
 int Engine::round(int nsteps, bool multi_only) {
     bool forked = false;
     if (multi_only) {
@@ -886,13 +895,15 @@ int Engine::round(int nsteps, bool multi_only) {
         CGS_HIP(hipStreamWaitEvent(side, ev_fork, 0));
         hipStream_t main_stream = stream;
         stream = side;
-        fused_steps(nsteps, 1);
+        for (int done = 0; done < nsteps; done += st.check_every)
+            fused_steps(std::min(st.check_every, nsteps - done), 1);
         stream = main_stream;
         CGS_HIP(hipGetLastError());
         CGS_HIP(hipEventRecord(ev_join, side));
         forked = true;
     } else if (n_fused) {
-        fused_steps(nsteps, 1);
+        for (int done = 0; done < nsteps; done += st.check_every)
+            fused_steps(std::min(st.check_every, nsteps - done), 1);
     }
     if (!n_multi) {
         CGS_HIP(hipGetLastError());
@@ -916,7 +927,7 @@ int Engine::round(int nsteps, bool multi_only) {
     // Capture and instantiation cost more than launching one round directly,
     // so a graph is captured only for tables that have already served a round
     // (a server rebuilds them whenever requests arrive or leave).
-    const bool use_g = st.use_graph && stream != nullptr && nsteps == st.check_every &&
+    const bool use_g = st.use_graph && stream != nullptr && nsteps == round_steps() &&
                        (!graphs.empty() || rounds_since_build >= 1);
     ++rounds_since_build;
     if (use_g) {
@@ -934,8 +945,7 @@ int Engine::round(int nsteps, bool multi_only) {
             }
             CGS_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
             if (spec) launch_snapshot(prec, T, 0, stream);
-            for (int i = 0; i < nsteps; ++i) admm_step();
-            check();
+            steps_with_checks(nsteps);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(stream, &g);
             if (e != hipSuccess) return fail(CGS_EHIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -952,8 +962,7 @@ int Engine::round(int nsteps, bool multi_only) {
         CGS_HIP(hipGraphLaunch(hit->exec, stream));
     } else {
         if (spec) launch_snapshot(prec, T, 0, stream);
-        for (int i = 0; i < nsteps; ++i) admm_step();
-        check();
+        steps_with_checks(nsteps);
     }
     spec_now = false;
     if (forked) CGS_HIP(hipStreamWaitEvent(stream, ev_join, 0));

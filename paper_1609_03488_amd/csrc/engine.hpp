@@ -244,12 +244,17 @@ class Engine {
     double setup_tol() const { return precision == CGS_FP64 ? std::min(st.setup_tol, 1e-10) : st.setup_tol; }
     void admm_step();
     void fused_steps(int nsteps, int check);
+    // steps of a round: intervals_per_sync check intervals
+    int round_steps() const { return st.check_every * std::max(1, st.intervals_per_sync); }
+    // nsteps ADMM steps with the termination test after every check_every of them
+    void steps_with_checks(int nsteps);
     void check(int gate = G_CHECK);
     void refresh();
     void adapt_cg();
     // ---- host loops
     int setup();                  // instances with phase 0 (synchronises)
-    // nsteps ADMM steps + termination test (enqueue); reads scal_host, so it
+    // nsteps ADMM steps, a termination test after every check_every of them and
+    // at the end (enqueue); reads scal_host, so it
     // follows fetch_scalars.  multi_only: the one-launch-per-kernel instances only
     int round(int nsteps, bool multi_only = false);
     // after fetch_scalars: the last round ran fewer CG launches per step than
