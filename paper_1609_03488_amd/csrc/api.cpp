@@ -418,9 +418,9 @@ int cgs_solver_kernel_time(cgs_solver* s, int32_t kernel, int32_t reps, double* 
             if (e.use_gemm) {
                 // the batch's dense applies: pack + BF16 MFMA GEMM + reduce
                 for (const cgs::DenseBlock& db : s->opdev.dense)
-                    cgs::launch_gemm_apply(e.inst_dev, e.T.ninst, db, adj, adj ? cgs::XT : cgs::YT,
-                                           adj ? cgs::YU : cgs::XU, 1.0, cgs::G_ALL, e.gemm_corr,
-                                           e.panel, e.panel_stride, e.gemm_part, e.gemm_target, e.stream),
+                    cgs::launch_gemm_apply(e.T, db, adj, adj ? cgs::XT : cgs::YT, adj ? cgs::YU : cgs::XU, 1.0,
+                                           cgs::G_ALL, e.gemm_corr, e.panel, e.panel_stride, e.gemm_part,
+                                           e.gemm_target, e.stream),
                         ++launches;
             } else {
                 for (const auto& d : dl)

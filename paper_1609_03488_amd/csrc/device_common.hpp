@@ -476,19 +476,80 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
         if (olo[j] <= lo && ohi[j] > lo) lo = ohi[j] < hi ? ohi[j] : hi;
         if (olo[j] < hi && ohi[j] >= hi) hi = olo[j] > lo ? olo[j] : lo;
     }
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        bool owned = false;
-        for (int j = 0; j < nown; ++j) owned = owned || (i >= olo[j] && i < ohi[j]);
-        if (owned) continue;
-        double v = bs ? (double)bs[i] : 0.0;
-        for (int b = d.id0; b < d.id1; ++b) {
-            const IdBlock ib = tb.ids[b];
-            const int64_t r0 = adj ? ib.col0 : ib.row0;
-            const int64_t c0 = adj ? ib.row0 : ib.col0;
-            if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
+    // The identity blocks that reach [lo, hi) (at most IB of them; more take
+    // the element-by-element loop).  Each thread then handles U elements at a
+    // time with all their loads issued before the first addition: element by
+    // element, every load would wait for the previous element's store.  The
+    // additions keep the order of the plain form, base first, then the blocks
+    // in table order.
+    constexpr int IB = 4, U = 8;
+    int64_t br0[IB], bc0[IB], bhi[IB];
+    double bw[IB];
+    int nb = 0;
+    bool many = false;
+    for (int b = d.id0; b < d.id1; ++b) {
+        const IdBlock ib = tb.ids[b];
+        const int64_t r0 = adj ? ib.col0 : ib.row0;
+        if (ib.len <= 0 || r0 >= hi || r0 + ib.len <= lo) continue;
+        if (nb == IB) {
+            many = true;
+            break;
         }
-        if (fold) fold_elem<T>(d, fold, fr, fp, fq, out, i, v, f);
-        else o[i] = (T)v;
+        br0[nb] = r0;
+        bc0[nb] = adj ? ib.row0 : ib.col0;
+        bhi[nb] = r0 + ib.len;
+        bw[nb] = sigma * ib.scale;
+        ++nb;
+    }
+    if (many) {
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            bool owned = false;
+            for (int j = 0; j < nown; ++j) owned = owned || (i >= olo[j] && i < ohi[j]);
+            if (owned) continue;
+            double v = bs ? (double)bs[i] : 0.0;
+            for (int b = d.id0; b < d.id1; ++b) {
+                const IdBlock ib = tb.ids[b];
+                const int64_t r0 = adj ? ib.col0 : ib.row0;
+                const int64_t c0 = adj ? ib.row0 : ib.col0;
+                if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
+            }
+            if (fold) fold_elem<T>(d, fold, fr, fp, fq, out, i, v, f);
+            else o[i] = (T)v;
+        }
+        return;
+    }
+    const int64_t step = (int64_t)blockDim.x;
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += U * step) {
+        T bv[U], sv[IB][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * step;
+            bv[u] = bs ? bs[i < hi ? i : lo] : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < IB; ++j) {
+            if (j >= nb) break;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t i = i0 + u * step;
+                const bool in_b = i < hi && i >= br0[j] && i < bhi[j];
+                sv[j][u] = src[in_b ? i - br0[j] + bc0[j] : bc0[j]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * step;
+            if (i >= hi) break;
+            bool owned = false;
+            for (int j = 0; j < nown; ++j) owned = owned || (i >= olo[j] && i < ohi[j]);
+            if (owned) continue;
+            double v = bs ? (double)bv[u] : 0.0;
+#pragma unroll
+            for (int j = 0; j < IB; ++j)
+                if (j < nb && i >= br0[j] && i < bhi[j]) v += bw[j] * (double)sv[j][u];
+            if (fold) fold_elem<T>(d, fold, fr, fp, fq, out, i, v, f);
+            else o[i] = (T)v;
+        }
     }
 }
 template <typename T>

@@ -738,13 +738,20 @@ void Engine::conv(const ConvLaunch& c, int adj, int out, int in, int base, doubl
 }
 
 void Engine::apply(int adj, int out, int in, int base, double sigma, int gate) {
-    if (!fold_init[adj]) launch_apply_init(prec, T, adj, out, in, base, sigma, gate, stream);
-    for (const auto& c : adj ? ca : cf) conv(c, adj, out, in, base, sigma, gate);
+    const auto& cl = adj ? ca : cf;
+    // with no convolution launch in between, the first GEMM's packing launch
+    // also writes the output's initial value
+    const bool init_in_pack = use_gemm && cl.empty() && !fold_init[adj] && !recs[0].op->dense.empty();
+    if (!fold_init[adj] && !init_in_pack) launch_apply_init(prec, T, adj, out, in, base, sigma, gate, stream);
+    for (const auto& c : cl) conv(c, adj, out, in, base, sigma, gate);
     if (use_gemm) {
         // every instance shares the dense blocks: one MFMA GEMM per block
-        for (const DenseBlock& db : recs[0].op->dense)
-            launch_gemm_apply(inst_dev, T.ninst, db, adj, out, in, sigma, gate, gemm_corr, panel,
-                              panel_stride, gemm_part, gemm_target, stream);
+        bool first = true;
+        for (const DenseBlock& db : recs[0].op->dense) {
+            launch_gemm_apply(T, db, adj, out, in, sigma, gate, gemm_corr, panel, panel_stride, gemm_part,
+                              gemm_target, stream, first && init_in_pack, base);
+            first = false;
+        }
     } else {
         for (const auto& d : adj ? da : df) launch_gemv(prec, T, d, adj, out, in, sigma, gate, stream);
     }

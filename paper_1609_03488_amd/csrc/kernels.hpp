@@ -188,11 +188,13 @@ void launch_gemm_pack_w(const float* w, int64_t rows, int64_t kpad, uint16_t* hi
 GemmPlan gemm_plan(int64_t N, int64_t kpad, int ninst, int target_wgs);
 constexpr int GEMM_TARGET_MAX = 1024;   // largest target the autotuner tries (sizes the partials)
 size_t gemm_part_bytes(const GemmPlan& g);
-// out_b += sigma * scale * W x_b for every instance b (W = A, or A^T when adj),
-// W in BF16 (plus refinement products when corr); panel_hi/lo hold
-// mpad x kpad BF16 values, part the split-K partials.
-void launch_gemm_apply(const InstDesc* insts, int ninst, const DenseBlock& db, int adj, int out, int in,
-                       double sigma, int gate, int corr, uint16_t* panel, size_t panel_stride,
-                       float* part, int target_wgs, hipStream_t st);
+// out_b += sigma * scale * W x_b for every instance b of the tables (W = A, or
+// A^T when adj), W in BF16 (plus refinement products when corr); panel holds
+// three mpad x kpad BF16 panels, part the split-K partials.  With init the
+// packing launch also writes the output's initial value (base + identity
+// blocks, as launch_apply_init) before the products are added.
+void launch_gemm_apply(const Tables& tb, const DenseBlock& db, int adj, int out, int in, double sigma,
+                       int gate, int corr, uint16_t* panel, size_t panel_stride, float* part,
+                       int target_wgs, hipStream_t st, bool init = false, int base = -1);
 
 }  // namespace cgs
