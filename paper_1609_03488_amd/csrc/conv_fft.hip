@@ -167,7 +167,7 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         const VecTile it = cl.init[blockIdx.x - cl.nftiles];
         const InstDesc di = tb.inst[it.inst];
         if (!gate_ok(scal(di), gate)) return;
-        init_tile<float>(tb, di, it, adj, out, in, base, sigma, FOLD, cl.fr, cl.fp, cl.fq, f);
+        init_tile<float, false>(tb, di, it, adj, out, in, base, sigma, FOLD, cl.fr, cl.fp, cl.fq, f);
         if (FOLD) fold_partials(cl.part, f, red);
         return;
     }

@@ -456,7 +456,10 @@ DEVI void fold_elem(const InstDesc& d, int mode, int fr, int fp, int fq, int out
     }
 }
 
-template <typename T>
+// BATCH: loads of several elements in flight (a kernel of its own); without
+// it the element loop, for initialisation tiles riding on long kernels, where
+// the batched loop's code and registers would cost the kernel's main path.
+template <typename T, bool BATCH = true>
 DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int adj, int out, int in,
                     int base, double sigma, int fold, int fr, int fp, int fq, Fold4& f) {
     gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
@@ -487,7 +490,7 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
     double bw[IB];
     int nb = 0;
     bool many = false;
-    for (int b = d.id0; b < d.id1; ++b) {
+    for (int b = d.id0; BATCH && b < d.id1; ++b) {
         const IdBlock ib = tb.ids[b];
         const int64_t r0 = adj ? ib.col0 : ib.row0;
         if (ib.len <= 0 || r0 >= hi || r0 + ib.len <= lo) continue;
@@ -501,7 +504,7 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
         bw[nb] = sigma * ib.scale;
         ++nb;
     }
-    if (many) {
+    if (many || !BATCH) {
         for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
             bool owned = false;
             for (int j = 0; j < nown; ++j) owned = owned || (i >= olo[j] && i < ohi[j]);
