@@ -252,7 +252,11 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         return;
     }
     constexpr int NE = 16;   // two windows x 8 values
-    int64_t gi[NE];          // block-local output index, -1: none
+    // Output positions as 32-bit offsets from the pair's first output oa
+    // (window a: j, window b: B + j; -1: none); the block's outputs start at
+    // g0 in the output vector.
+    const int nlim = n_out - oa < 2 * (int64_t)B ? (int)(n_out - oa) : 2 * B;
+    int li[NE];
     double res[NE];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -260,33 +264,34 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         for (int r = 0; r < 4; ++r) {
             const int e = 4 * h + r;
             const int j = t + FT * h + 512 * r;
-            const int64_t ia = oa + j, ib = ob + j;
-            gi[2 * e] = (j < B && ia < n_out) ? ia : -1;
-            gi[2 * e + 1] = (j < B && ib < n_out) ? ib : -1;
+            li[2 * e] = (j < B && j < nlim) ? j : -1;
+            li[2 * e + 1] = (j < B && B + j < nlim) ? B + j : -1;
             res[2 * e] = (double)v[e].x;
             res[2 * e + 1] = -(double)v[e].y;
         }
+    gptr<float> ow = o + oa;
     if (!own) {
         double old[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) old[e] = (double)o[gi[e] >= 0 ? gi[e] : 0];
+        for (int e = 0; e < NE; ++e) old[e] = (double)ow[li[e] >= 0 ? li[e] : 0];
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (gi[e] >= 0) o[gi[e]] = (float)(old[e] + s * res[e]);
+            if (li[e] >= 0) ow[li[e]] = (float)(old[e] + s * res[e]);
         return;
     }
+    const int64_t gw = g0 + oa;   // output vector position of offset 0
     // base + identity blocks of the owned range
     double bv[NE];
     {
-        // (loads are unconditional, at the block's first element where the
+        // (loads are unconditional, at the pair's first output where the
         // thread has no output, so that none sits behind a branch)
         if (base >= 0) {
-            gptr<const float> bp = adj ? xvec<float>(d, base) : yvec<float>(d, base);
+            gptr<const float> bp = (adj ? xvec<float>(d, base) : yvec<float>(d, base)) + gw;
             float l[NE];
 #pragma unroll
-            for (int e = 0; e < NE; ++e) l[e] = bp[g0 + (gi[e] >= 0 ? gi[e] : 0)];
+            for (int e = 0; e < NE; ++e) l[e] = bp[li[e] >= 0 ? li[e] : 0];
 #pragma unroll
-            for (int e = 0; e < NE; ++e) bv[e] = gi[e] >= 0 ? (double)l[e] : 0.0;
+            for (int e = 0; e < NE; ++e) bv[e] = li[e] >= 0 ? (double)l[e] : 0.0;
         } else {
 #pragma unroll
             for (int e = 0; e < NE; ++e) bv[e] = 0.0;
@@ -296,65 +301,67 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
             const IdBlock ib = tb.ids[b];
             const int64_t r0 = adj ? ib.col0 : ib.row0;
             // blocks that miss the workgroup's outputs [oa, oa + 2B) issue no load
-            if (ib.len <= 0 || r0 >= g0 + oa + 2 * (int64_t)B || r0 + ib.len <= g0 + oa) continue;
+            if (ib.len <= 0 || r0 >= gw + 2 * (int64_t)B || r0 + ib.len <= gw) continue;
             const int64_t c0 = adj ? ib.row0 : ib.col0;
             const double w = sigma * ib.scale;
+            // the block's rows as offsets, clamped to [0, 2B]
+            const int64_t rl = r0 - gw, rh = r0 + ib.len - gw;
+            const int lo = rl < 0 ? 0 : (int)rl;
+            const int hi = rh > 2 * (int64_t)B ? 2 * B : (int)rh;
+            gptr<const float> iw = isrc + (c0 - r0 + gw);
             float l[NE];
 #pragma unroll
             for (int e = 0; e < NE; ++e) {
-                const int64_t g = g0 + gi[e];
-                const bool in_r = gi[e] >= 0 && g >= r0 && g < r0 + ib.len;
-                l[e] = isrc[in_r ? g - r0 + c0 : c0];
+                const bool in_r = li[e] >= lo && li[e] < hi;
+                l[e] = in_r ? iw[li[e]] : isrc[c0];
             }
 #pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const int64_t g = g0 + gi[e];
-                if (gi[e] >= 0 && g >= r0 && g < r0 + ib.len) bv[e] += w * (double)l[e];
-            }
+            for (int e = 0; e < NE; ++e)
+                if (li[e] >= lo && li[e] < hi) bv[e] += w * (double)l[e];
         }
     }
     if (FOLD == 0) {
 #pragma unroll
         for (int e = 0; e < NE; ++e)
-            if (gi[e] >= 0) o[gi[e]] = (float)(bv[e] + s * res[e]);
+            if (li[e] >= 0) ow[li[e]] = (float)(bv[e] + s * res[e]);
         return;
     }
     // (a folded launch owns every X element)
     if (FOLD == 1) {
         // h = value; r = h - K z, p = r written instead of h
-        gptr<const float> kz = xvec<float>(d, cl.fq);
+        gptr<const float> kz = xvec<float>(d, cl.fq) + gw;
         float kv[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) kv[e] = kz[g0 + (gi[e] >= 0 ? gi[e] : 0)];
-        gptr<float> rv = xvec<float>(d, cl.fr);
-        gptr<float> pv = xvec<float>(d, cl.fp);
+        for (int e = 0; e < NE; ++e) kv[e] = kz[li[e] >= 0 ? li[e] : 0];
+        gptr<float> rv = xvec<float>(d, cl.fr) + gw;
+        gptr<float> pv = xvec<float>(d, cl.fp) + gw;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            if (gi[e] < 0) continue;
+            if (li[e] < 0) continue;
             const float hv = (float)(bv[e] + s * res[e]);
             const double hd = (double)hv;
             const float rr = (float)(hd - (double)kv[e]);
-            rv[g0 + gi[e]] = rr;
-            pv[g0 + gi[e]] = rr;
+            rv[li[e]] = rr;
+            pv[li[e]] = rr;
             f.a += (double)rr * (double)rr;
             f.b += hd * hd;
         }
     } else {
         // q = value; partials <p, q>, ||r||^2, <r, q>, ||q||^2
-        gptr<const float> pp = xvec<float>(d, cl.fp);
-        gptr<const float> rp = xvec<float>(d, cl.fr);
+        gptr<const float> pp = xvec<float>(d, cl.fp) + gw;
+        gptr<const float> rp = xvec<float>(d, cl.fr) + gw;
         float pvv[NE], rvv[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            pvv[e] = pp[g0 + (gi[e] >= 0 ? gi[e] : 0)];
-            rvv[e] = rp[g0 + (gi[e] >= 0 ? gi[e] : 0)];
+            pvv[e] = pp[li[e] >= 0 ? li[e] : 0];
+            rvv[e] = rp[li[e] >= 0 ? li[e] : 0];
         }
-        gptr<float> qo = xvec<float>(d, out);
+        gptr<float> qo = xvec<float>(d, out) + gw;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            if (gi[e] < 0) continue;
+            if (li[e] < 0) continue;
             const float q = (float)(bv[e] + s * res[e]);
-            qo[g0 + gi[e]] = q;
+            qo[li[e]] = q;
             const double pd = (double)pvv[e], rd = (double)rvv[e], qd = (double)q;
             f.a = fma(pd, qd, f.a);
             f.b = fma(rd, rd, f.b);
