@@ -82,8 +82,8 @@ constexpr int XY_ALIGN = 64; // elements
 constexpr int REGION_HDR = NSC * 8 + NCNT * 4;  // 512 bytes
 // vectors of that copy: u_x, z, K z and u_y, v_s, w_y, A z (every other vector
 // is either constant during the iteration or written before it is read in a step)
-constexpr int SNAP_X = 3;
-constexpr int SNAP_Y = 4;
+constexpr int SNAP_X = 2;   // u_x, z (the CG warm start)
+constexpr int SNAP_Y = 2;   // u_y, v_s
 
 // ---------------------------------------------------------------- gates
 enum Gate : int {
@@ -117,7 +117,10 @@ struct InstDesc {
     int32_t cp0, cp1, ip0, ip1;
     // copy of the state carried from one ADMM step to the next, taken at the
     // start of a check interval run with fewer CG launches per step than the
-    // iteration limit (null: none): [header | SNAP_X vectors of nxs | SNAP_Y of nys]
+    // iteration limit (null: none): [header | SNAP_X vectors of nxs | SNAP_Y of nys].
+    // The rest of the carried state (w_y = u_y + v_s, A z and (I + A^T A) z)
+    // is a function of these, formed exactly by the check that precedes every
+    // such interval, and is formed again the same way on a restore.
     char* snap;
 };
 

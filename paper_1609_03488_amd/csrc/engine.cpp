@@ -986,6 +986,10 @@ bool Engine::truncated() const {
 
 int Engine::rollback() {
     launch_snapshot(prec, T, 1, stream);
+    // w_y, A z and z + A^T A z as the check before the interval formed them
+    launch_wy(prec, T, G_ADMM, stream);
+    apply(0, YA, XZ, -1, 1.0, G_ADMM);
+    apply(1, XK, YA, XZ, 1.0, G_ADMM);
     CGS_HIP(hipGetLastError());
     ++n_reruns;
     cg_launch = std::min(st.cg_max_iters, 2 * spec_launch + 1);

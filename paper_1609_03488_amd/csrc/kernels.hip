@@ -913,8 +913,7 @@ __global__ __launch_bounds__(VEC_NT) void k_snapshot(Tables tb, int restore) {
     const int64_t lo = xt.t.start, hi = xt.t.start + xt.t.len;
     const int nv = xt.is_y ? SNAP_Y : SNAP_X;
     for (int v = 0; v < nv; ++v) {
-        gptr<T> live = xt.is_y ? yvec<T>(d, v == 0 ? YU : v == 1 ? YV : v == 2 ? YW : YA)
-                               : xvec<T>(d, v == 0 ? XU : v == 1 ? XZ : XK);
+        gptr<T> live = xt.is_y ? yvec<T>(d, v == 0 ? YU : YV) : xvec<T>(d, v == 0 ? XU : XZ);
         gptr<T> kept = xt.is_y ? cy + (int64_t)v * d.nys : cx + (int64_t)v * d.nxs;
         gptr<T> dst = restore ? live : kept;
         gptr<const T> src = restore ? kept : live;
