@@ -72,21 +72,35 @@ DEVI void dft8(cf* v) {
 constexpr int LDS_L = FFT_L + FFT_L / 32;
 DEVI int lp(int i) { return i + (i >> 5); }
 
-// tw[i] = e^{-2 pi i i / FFT_L}, filled by every workgroup (8 values per thread)
+// Twiddle factors e^{-2 pi i m / FFT_L}, stored per stage in the order the
+// lanes read them: entry (r - 1) * Ns + k holds the factor of butterfly input
+// r for k = thread % Ns, so the lanes of a wave read consecutive entries (a
+// table indexed by m would put the lanes of one stage 32 or 256 bytes apart,
+// in the same few LDS banks).  Stages Ns = 8 and 64 (radix 8, m = r k FFT_L /
+// (8 Ns)) and the radix-4 stage (m = r j, j < 512); every entry is the value
+// the m-indexed table would hold.
+constexpr int TW8 = 0, TW64 = 7 * 8, TW512 = TW64 + 7 * 64, TW_N = TW512 + 3 * 512;
+DEVI int tw_index(int e) {   // entry -> m
+    if (e < TW64) return ((e / 8 + 1) * (e % 8) * (FFT_L / 64)) & (FFT_L - 1);
+    if (e < TW512) return (((e - TW64) / 64 + 1) * ((e - TW64) % 64) * (FFT_L / 512)) & (FFT_L - 1);
+    return (((e - TW512) / 512 + 1) * ((e - TW512) % 512)) & (FFT_L - 1);
+}
+// filled by every workgroup (8 values per thread)
 DEVI void fill_twiddles(cf* tw) {
 #pragma unroll
-    for (int r = 0; r < FFT_L / FT; ++r) {
-        const int i = threadIdx.x + FT * r;
+    for (int r = 0; r < (TW_N + FT - 1) / FT; ++r) {
+        const int e = threadIdx.x + FT * r;
+        if (e >= TW_N) break;
         float s, c;
-        sincospif(-2.0f * (float)i / (float)FFT_L, &s, &c);
-        tw[i] = {c, s};
+        sincospif(-2.0f * (float)tw_index(e) / (float)FFT_L, &s, &c);
+        tw[e] = {c, s};
     }
 }
+// v[r] *= factor (r - 1) of the stage table `t` (stride n), r = 1 .. R-1
 template <int R>
-DEVI void twiddle(cf* v, int k, int span, const cf* tw) {   // v[r] *= e^{-2 pi i r k / span}
-    const int step = k * (FFT_L / span);
+DEVI void twiddle(cf* v, const cf* t, int n) {
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[(r * step) & (FFT_L - 1)]);
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], t[(r - 1) * n]);
 }
 
 // Forward DFT of the 2048 values x[t + 256 r] that thread t holds in v[r].
@@ -104,7 +118,7 @@ DEVI void fft2048(cf* v, cf* lds, const cf* tw) {
 #pragma unroll
         for (int r = 0; r < 8; ++r) v[r] = lds[lp(t + FT * r)];
         const int k = t % Ns;
-        twiddle<8>(v, k, Ns * 8, tw);
+        twiddle<8>(v, tw + (Ns == 8 ? TW8 : TW64) + k, Ns);
         dft8(v);
         __syncthreads();
         const int base = (t / Ns) * Ns * 8 + k;
@@ -119,7 +133,7 @@ DEVI void fft2048(cf* v, cf* lds, const cf* tw) {
         cf* w = v + 4 * h;
 #pragma unroll
         for (int r = 0; r < 4; ++r) w[r] = lds[lp(j + 512 * r)];
-        twiddle<4>(w, j, 2048, tw);
+        twiddle<4>(w, tw + TW512 + j, 512);
         dft4(w);
     }
     __syncthreads();
@@ -140,7 +154,7 @@ DEVI void fold_partials(double* part, const Fold4& f, double* red) {
 // conj(DFT(w zero-padded to FFT_L)) of k correlation-order taps
 __global__ __launch_bounds__(FT) void k_conv_spectrum(const float* w, int k, float2* spec) {
     __shared__ cf lds[LDS_L];
-    __shared__ cf tw[FFT_L];
+    __shared__ cf tw[TW_N];
     const int t = threadIdx.x;
     fill_twiddles(tw);
     cf v[8];
@@ -160,7 +174,7 @@ template <int FOLD>
 __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int adj, int out, int in, int base,
                                                  double sigma, int gate) {
     __shared__ cf lds[LDS_L];
-    __shared__ cf tw[FFT_L];
+    __shared__ cf tw[TW_N];
     __shared__ double red[4 * (FT / 64)];
     Fold4 f{0.0, 0.0, 0.0, 0.0};
     if ((int)blockIdx.x >= cl.nftiles) {   // initialisation tiles riding on the launch
