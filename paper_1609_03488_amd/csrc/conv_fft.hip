@@ -210,16 +210,21 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         src = yvec<float>(d, in) + cb.row0;
     }
     const int t = threadIdx.x;
-    fill_twiddles(tw);
     const int B = FFT_L - (int)cb.k + 1;   // outputs per window
-    const int64_t oa = tl.start, ob = tl.start + B;
+    const int64_t oa = tl.start;
+    // the pair's inputs as 32-bit offsets q = p (window a) and B + p (window b)
+    // from input position oa + off; valid offsets [qlo, qhi)
+    const int64_t i0 = oa + off;
+    const int qlo = i0 < 0 ? (int)-i0 : 0;
+    const int qhi = n_in - i0 < FFT_L + B ? (int)(n_in - i0) : FFT_L + B;
+    gptr<const float> sw = src + i0;
     cf v[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int p = t + FT * r;
-        const int64_t ga = oa + off + p, gb = ob + off + p;
-        v[r] = {(ga >= 0 && ga < n_in) ? src[ga] : 0.0f, (gb >= 0 && gb < n_in) ? src[gb] : 0.0f};
+        v[r] = {(p >= qlo && p < qhi) ? sw[p] : 0.0f, (B + p >= qlo && B + p < qhi) ? sw[B + p] : 0.0f};
     }
+    fill_twiddles(tw);
     fft2048(v, lds, tw);
     // product with conj(DFT(w)), conjugated: the inverse is a forward transform
     gptr<const float> sp = (gptr<const float>)spec;   // interleaved (re, im)
@@ -251,6 +256,11 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         const int64_t r0 = adj ? ib.col0 : ib.row0;
         id_hit = id_hit || (ib.len > 0 && r0 < g0 + oa + 2 * (int64_t)B && r0 + ib.len > g0 + oa);
     }
+    // Output positions as 32-bit offsets from the pair's first output oa
+    // (window a: j, window b: B + j); offsets below nlim exist.  The block's
+    // outputs start at g0 in the output vector.
+    const int nlim = n_out - oa < 2 * (int64_t)B ? (int)(n_out - oa) : 2 * B;
+    gptr<float> ow = o + oa;
     if (FOLD == 0 && own && base < 0 && !id_hit) {
         // nothing to load: the outputs are the sums alone
 #pragma unroll
@@ -259,17 +269,13 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
             for (int r = 0; r < 4; ++r) {
                 const int j = t + FT * h + 512 * r;
                 if (j >= B) continue;
-                const int64_t ia = oa + j, ib = ob + j;
-                if (ia < n_out) o[ia] = (float)(0.0 + s * (double)v[4 * h + r].x);
-                if (ib < n_out) o[ib] = (float)(0.0 + s * -(double)v[4 * h + r].y);
+                if (j < nlim) ow[j] = (float)(0.0 + s * (double)v[4 * h + r].x);
+                if (B + j < nlim) ow[B + j] = (float)(0.0 + s * -(double)v[4 * h + r].y);
             }
         return;
     }
     constexpr int NE = 16;   // two windows x 8 values
-    // Output positions as 32-bit offsets from the pair's first output oa
-    // (window a: j, window b: B + j; -1: none); the block's outputs start at
-    // g0 in the output vector.
-    const int nlim = n_out - oa < 2 * (int64_t)B ? (int)(n_out - oa) : 2 * B;
+    // (-1: no output)
     int li[NE];
     double res[NE];
 #pragma unroll
@@ -283,7 +289,6 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
             res[2 * e] = (double)v[e].x;
             res[2 * e + 1] = -(double)v[e].y;
         }
-    gptr<float> ow = o + oa;
     if (!own) {
         double old[NE];
 #pragma unroll
