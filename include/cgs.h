@@ -81,6 +81,14 @@ enum {
 /* Block kinds of an operator description. */
 enum { CGS_BLOCK_IDENTITY = 0, CGS_BLOCK_CONV = 1, CGS_BLOCK_DENSE = 2 };
 
+/* Element types and memory kinds of a dense block (cgs_op_add_dense_ex). */
+enum { CGS_DTYPE_F64 = 0, CGS_DTYPE_F32 = 1 };
+enum {
+    CGS_MEM_HOST_COPY = 0,      /* host array, copied by the call                   */
+    CGS_MEM_DEVICE_BORROW = 1   /* device array on the current device, read in
+                                   place (never copied to the host)              */
+};
+
 typedef struct cgs_op cgs_op;
 typedef struct cgs_solver cgs_solver;
 typedef struct cgs_server cgs_server;
@@ -218,6 +226,25 @@ int cgs_op_add_conv(cgs_op* op, int64_t row0, int64_t col0, const double* taps, 
  * (copied; converted to the solver's precision at solver creation). */
 int cgs_op_add_dense(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64_t cols,
                      const double* a, int64_t lda, double scale);
+/* The same block from typed memory (Section III: a dense block is one of the
+ * structured pieces the operator is composed of; this call only chooses where
+ * its entries come from).  dtype: CGS_DTYPE_F64 or CGS_DTYPE_F32 (FP32 host
+ * data is widened to FP64 exactly).  mem:
+ *   CGS_MEM_HOST_COPY     a is a host array, validated and copied now;
+ *   CGS_MEM_DEVICE_BORROW a is device memory of the current device (for
+ *                         instance a torch tensor's data).  The call reads it
+ *                         once on the device to validate it (every entry
+ *                         finite) and to form its Frobenius norm; every solver
+ *                         and server created from this operator reads it again
+ *                         at creation (conversion to the working precision,
+ *                         transpose, BF16 copies) on its own stream.  The
+ *                         caller keeps the memory allocated and unchanged until
+ *                         cgs_op_destroy; the library never frees it.
+ * lda >= cols elements.  Errors: CGS_EINVAL (null a, unknown dtype or mem, a
+ * non-finite entry, a borrowed pointer that is not device memory of the
+ * current device), CGS_EDIM (bad shape or lda), CGS_EHIP (device failure). */
+int cgs_op_add_dense_ex(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64_t cols,
+                        const void* a, int64_t lda, int32_t dtype, int32_t mem, double scale);
 /* Number of blocks and the operator size. */
 int cgs_op_info(const cgs_op* op, int64_t* m, int64_t* n, int64_t* nblocks);
 /* The scaling a solver with normalize = level applies to this operator and

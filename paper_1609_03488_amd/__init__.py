@@ -8,7 +8,7 @@ binding raises if the library is missing.
 """
 from ._lib import (  # noqa: F401
     CgsError, Settings, Info, Operator, Solver, Server, lib, library_path, solve_noalloc,
-    NOALLOC_SCRATCH_BYTES,
+    NOALLOC_SCRATCH_BYTES, DTYPE_F64, DTYPE_F32, MEM_HOST_COPY, MEM_DEVICE_BORROW,
     FP64, FP32, BF16, SOLVED, MAX_ITERS, INFEASIBLE, UNBOUNDED, NUMERICAL, RUNNING,
     STATUS_NAMES,
 )

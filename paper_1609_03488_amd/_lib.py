@@ -11,6 +11,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libcgs.so")
 
 FP64, FP32, BF16 = 0, 1, 2
+DTYPE_F64, DTYPE_F32 = 0, 1            # CGS_DTYPE_*
+MEM_HOST_COPY, MEM_DEVICE_BORROW = 0, 1  # CGS_MEM_*
 RUNNING, SOLVED, MAX_ITERS, INFEASIBLE, UNBOUNDED, NUMERICAL = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {RUNNING: "running", SOLVED: "solved", MAX_ITERS: "max_iters",
                 INFEASIBLE: "infeasible", UNBOUNDED: "unbounded", NUMERICAL: "numerical"}
@@ -75,6 +77,7 @@ _SIGS = {
     "cgs_op_add_identity": (C.c_int, [_P, _I64, _I64, _I64, _D]),
     "cgs_op_add_conv": (C.c_int, [_P, _I64, _I64, _DP, _I64, _I64, _D]),
     "cgs_op_add_dense": (C.c_int, [_P, _I64, _I64, _I64, _I64, _DP, _I64, _D]),
+    "cgs_op_add_dense_ex": (C.c_int, [_P, _I64, _I64, _I64, _I64, _P, _I64, C.c_int32, C.c_int32, _D]),
     "cgs_op_info": (C.c_int, [_P, _I64P, _I64P, _I64P]),
     "cgs_op_equilibrate": (C.c_int, [_P, C.c_int64, _I64P, C.c_int64, C.c_int32, _DP, _DP, _DP, _DP,
                                      _DP]),
@@ -174,6 +177,7 @@ class Operator:
         self._h = h
         self.m, self.n = int(m), int(n)
         self.kinds: List[str] = []
+        self._borrowed: list = []   # device tensors the operator reads in place
 
     def add_identity(self, row0: int, col0: int, length: int, scale: float = 1.0) -> "Operator":
         _check(lib().cgs_op_add_identity(self._h, row0, col0, length, float(scale)))
@@ -187,11 +191,38 @@ class Operator:
         return self
 
     def add_dense(self, row0: int, col0: int, a, scale: float = 1.0) -> "Operator":
-        a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        """Dense block.  ``a``: a 2-D array (FP64 or FP32 numpy data is copied),
+        or a 2-D torch tensor: on the GPU (FP32 or FP64, unit column stride) it
+        is borrowed -- read in place on the device, never copied to the host --
+        and this operator keeps a reference to it; the caller must not change
+        it while solvers are being created from the operator."""
+        try:
+            import torch
+            is_tensor = isinstance(a, torch.Tensor)
+        except ImportError:   # pragma: no cover
+            is_tensor = False
+        if is_tensor and a.is_cuda:
+            if a.dim() != 2 or a.dtype not in (torch.float32, torch.float64) or a.stride(1) != 1:
+                raise ValueError("a borrowed dense block must be a 2-D FP32/FP64 tensor with unit column stride")
+            dt = DTYPE_F32 if a.dtype == torch.float32 else DTYPE_F64
+            _check(lib().cgs_op_add_dense_ex(self._h, row0, col0, a.shape[0], a.shape[1], a.data_ptr(),
+                                             a.stride(0), dt, MEM_DEVICE_BORROW, float(scale)))
+            self._borrowed.append(a)
+            self.kinds.append("dense")
+            return self
+        if is_tensor:
+            a = a.numpy()
+        a = np.asarray(a)
         if a.ndim != 2:
             raise ValueError("dense block must be 2-D")
-        _check(lib().cgs_op_add_dense(self._h, row0, col0, a.shape[0], a.shape[1], _dp(a),
-                                      a.shape[1], float(scale)))
+        if a.dtype == np.float32:
+            a = np.ascontiguousarray(a)
+            _check(lib().cgs_op_add_dense_ex(self._h, row0, col0, a.shape[0], a.shape[1], a.ctypes.data,
+                                             a.shape[1], DTYPE_F32, MEM_HOST_COPY, float(scale)))
+        else:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            _check(lib().cgs_op_add_dense(self._h, row0, col0, a.shape[0], a.shape[1], _dp(a),
+                                          a.shape[1], float(scale)))
         self.kinds.append("dense")
         return self
 

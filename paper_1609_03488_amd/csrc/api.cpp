@@ -179,7 +179,15 @@ int cgs_op_add_conv(cgs_op* op, int64_t row0, int64_t col0, const double* taps, 
 
 int cgs_op_add_dense(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64_t cols,
                      const double* a, int64_t lda, double scale) {
+    return cgs_op_add_dense_ex(op, row0, col0, rows, cols, a, lda, CGS_DTYPE_F64, CGS_MEM_HOST_COPY, scale);
+}
+
+int cgs_op_add_dense_ex(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64_t cols,
+                        const void* a, int64_t lda, int32_t dtype, int32_t mem, double scale) {
     if (!a) return fail(CGS_EINVAL, "matrix is null");
+    if (dtype != CGS_DTYPE_F64 && dtype != CGS_DTYPE_F32) return fail(CGS_EINVAL, "unknown dtype %d", dtype);
+    if (mem != CGS_MEM_HOST_COPY && mem != CGS_MEM_DEVICE_BORROW)
+        return fail(CGS_EINVAL, "unknown memory kind %d", mem);
     CGS_TRY(check_block(op, row0, col0, rows, cols, scale));
     if (lda < cols) return fail(CGS_EDIM, "lda %lld < cols %lld", (long long)lda, (long long)cols);
     cgs::HostBlock b{};
@@ -189,18 +197,48 @@ int cgs_op_add_dense(cgs_op* op, int64_t row0, int64_t col0, int64_t rows, int64
     b.rows = rows;
     b.cols = cols;
     b.scale = scale;
+    if (mem == CGS_MEM_DEVICE_BORROW) {
+        hipPointerAttribute_t at{};
+        int cur = -1;
+        CGS_HIP(hipGetDevice(&cur));
+        if (hipPointerGetAttributes(&at, a) != hipSuccess || at.type != hipMemoryTypeDevice || at.device != cur) {
+            (void)hipGetLastError();
+            return fail(CGS_EINVAL, "a borrowed dense block must be device memory of the current device");
+        }
+        CGS_TRY(cgs::dense_frob2_device(a, dtype, rows, cols, lda, &b.frob2));
+        b.dev = a;
+        b.dev_dtype = dtype;
+        b.dev_ld = lda;
+        b.dev_id = cur;
+        op->blocks.push_back(std::move(b));
+        return CGS_OK;
+    }
     try {
         b.data.resize((size_t)(rows * cols));
     } catch (...) {
         return fail(CGS_ENOMEM, "host allocation of %lld doubles failed", (long long)(rows * cols));
     }
-    for (int64_t i = 0; i < rows; ++i) {
-        const double* src = a + i * lda;
-        if (!all_finite(src, cols)) return fail(CGS_EINVAL, "matrix row %lld has a non-finite value", (long long)i);
-        std::memcpy(b.data.data() + i * cols, src, (size_t)cols * sizeof(double));
-    }
+    // each row's squares in column order, then the row sums in row order (the
+    // order the device forms it in for a borrowed block)
     b.frob2 = 0.0;
-    for (double v : b.data) b.frob2 += v * v;
+    for (int64_t i = 0; i < rows; ++i) {
+        double* dst = b.data.data() + i * cols;
+        if (dtype == CGS_DTYPE_F64) {
+            const double* src = (const double*)a + i * lda;
+            if (!all_finite(src, cols)) return fail(CGS_EINVAL, "matrix row %lld has a non-finite value", (long long)i);
+            std::memcpy(dst, src, (size_t)cols * sizeof(double));
+        } else {
+            const float* src = (const float*)a + i * lda;
+            for (int64_t j = 0; j < cols; ++j) {
+                if (!std::isfinite(src[j]))
+                    return fail(CGS_EINVAL, "matrix row %lld has a non-finite value", (long long)i);
+                dst[j] = (double)src[j];
+            }
+        }
+        double rs = 0.0;
+        for (int64_t j = 0; j < cols; ++j) rs += dst[j] * dst[j];
+        b.frob2 += rs;
+    }
     op->blocks.push_back(std::move(b));
     return CGS_OK;
 }

@@ -70,7 +70,7 @@ int64_t staging_doubles(const cgs_op& op, int64_t max_vec) {
     int64_t need = std::max<int64_t>(max_vec, int64_t(1) << 16);
     for (const auto& b : op.blocks) {
         if (b.kind == CGS_BLOCK_CONV) need = std::max<int64_t>(need, 2 * round_up(b.k, 8));
-        if (b.kind == CGS_BLOCK_DENSE) {
+        if (b.kind == CGS_BLOCK_DENSE && b.dev == nullptr) {   // (a borrowed block needs none)
             need = std::max<int64_t>(need, std::min<int64_t>(b.rows * b.cols, int64_t(4) << 20));
             need = std::max<int64_t>(need, b.cols);
         }
@@ -309,14 +309,26 @@ int op_upload(const cgs_op& op, int precision, char* dst, const Staging& stg, hi
             db.at = p;
             p += align256(cols * ldt * sz);
             CGS_HIP(hipMemsetAsync(const_cast<void*>(db.at), 0, cols * ldt * sz, st));
+            if (b.dev != nullptr) {
+                // borrowed device memory: converted in place, no host round trip
+                int cur = -1;
+                CGS_HIP(hipGetDevice(&cur));
+                if (cur != b.dev_id)
+                    return fail(CGS_EINVAL, "a borrowed dense block lives on device %d, the solver on %d",
+                                b.dev_id, cur);
+                launch_cast_pad(prec, b.dev, b.dev_dtype, b.dev_ld, rows, cols, const_cast<void*>(db.a), ld, st);
+                launch_cast_transpose(prec, b.dev, b.dev_dtype, b.dev_ld, rows, cols, const_cast<void*>(db.at),
+                                      ldt, 0, st);
+                CGS_HIP(hipStreamSynchronize(st));
+            }
             const int64_t rpc = std::max<int64_t>(1, stg.cap / cols);
-            for (int64_t r0 = 0; r0 < rows; r0 += rpc) {
+            for (int64_t r0 = 0; b.dev == nullptr && r0 < rows; r0 += rpc) {
                 const int64_t nr = std::min(rpc, rows - r0);
                 std::memcpy(stg.host, b.data.data() + r0 * cols, (size_t)(nr * cols) * sizeof(double));
                 CGS_HIP(hipMemcpyAsync(stg.dev, stg.host, (size_t)(nr * cols) * sizeof(double),
                                        hipMemcpyHostToDevice, st));
-                launch_cast_pad(prec, stg.dev, nr, cols, (char*)db.a + r0 * ld * sz, ld, st);
-                launch_cast_transpose(prec, stg.dev, nr, cols, const_cast<void*>(db.at), ldt, r0, st);
+                launch_cast_pad(prec, stg.dev, 0, cols, nr, cols, (char*)db.a + r0 * ld * sz, ld, st);
+                launch_cast_transpose(prec, stg.dev, 0, cols, nr, cols, const_cast<void*>(db.at), ldt, r0, st);
                 CGS_HIP(hipStreamSynchronize(st));
             }
             if (precision == CGS_BF16) {

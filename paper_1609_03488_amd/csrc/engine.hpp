@@ -46,6 +46,12 @@ struct HostBlock {
     double scale;
     double frob2;             // sum of squares of the entries, scale excluded
     std::vector<double> data; // taps (k) or dense rows x cols (packed)
+    // a dense block borrowed from device memory (data empty): rows x cols
+    // entries of type dev_dtype, row stride dev_ld, on device dev_id
+    const void* dev = nullptr;
+    int dev_dtype = 0;
+    int64_t dev_ld = 0;
+    int dev_id = -1;
 };
 
 }  // namespace cgs

@@ -16,6 +16,11 @@
 //    the method (tau, kappa, eta, CG alpha/beta, norms, residuals) is FP64.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
+#include "cgs.h"
+
 #include <cmath>
 #include <cstdint>
 
@@ -968,19 +973,19 @@ __global__ void k_cast(const double* src, T* dst, int64_t n) {
         dst[i] = (T)src[i];
 }
 
-template <typename T>
-__global__ void k_cast_pad(const double* src, int64_t rows, int64_t cols, T* dst, int64_t ld) {
+template <typename S, typename T>
+__global__ void k_cast_pad(const S* src, int64_t lds, int64_t rows, int64_t cols, T* dst, int64_t ld) {
     const int64_t total = rows * ld;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = i / ld, c = i - r * ld;
-        dst[i] = c < cols ? (T)src[r * cols + c] : T(0);
+        dst[i] = c < cols ? (T)(double)src[r * lds + c] : T(0);
     }
 }
 
-// 32x32 LDS-tiled transpose of a row chunk: dst[c * ldt + r0 + r] = src[r * cols + c]
-template <typename T>
-__global__ __launch_bounds__(256) void k_cast_transpose(const double* src, int64_t rows,
+// 32x32 LDS-tiled transpose of a row chunk: dst[c * ldt + r0 + r] = src[r * lds + c]
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void k_cast_transpose(const S* src, int64_t lds, int64_t rows,
                                                         int64_t cols, T* dst, int64_t ldt,
                                                         int64_t r0) {
     __shared__ double tile[32][33];
@@ -988,13 +993,35 @@ __global__ __launch_bounds__(256) void k_cast_transpose(const double* src, int64
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     for (int j = ty; j < 32; j += 8) {
         const int64_t r = r_base + j, c = c_base + tx;
-        tile[j][tx] = (r < rows && c < cols) ? src[r * cols + c] : 0.0;
+        tile[j][tx] = (r < rows && c < cols) ? (double)src[r * lds + c] : 0.0;
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
         const int64_t c = c_base + j, r = r_base + tx;
         if (c < cols && r < rows) dst[c * ldt + r0 + r] = (T)tile[tx][j];
     }
+}
+
+// Row sums of squares of a device matrix, one thread per row, each summed in
+// column order (the host's order for a copied block); a non-finite entry
+// raises *bad.  Rows [r0, r0 + nr) into out[0, nr).
+template <typename S>
+__global__ __launch_bounds__(256) void k_dense_rowsq(const S* a, int64_t lda, int64_t r0, int64_t nr,
+                                                     int64_t cols, double* out, int* bad) {
+    // products and sums rounded separately, as the host's (which has no FMA)
+#pragma clang fp contract(off)
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    const S* row = a + (r0 + r) * lda;
+    double s = 0.0;
+    bool fin = true;
+    for (int64_t c = 0; c < cols; ++c) {
+        const double v = (double)row[c];
+        fin = fin && isfinite(v);
+        s += v * v;
+    }
+    out[r] = s;
+    if (!fin) atomicOr(bad, 1);
 }
 
 template <typename T>
@@ -1113,18 +1140,72 @@ void launch_cast(int prec, const double* src, void* dst, int64_t n, hipStream_t 
     if (prec == 0) k_cast<double><<<flat_grid(n, 256), 256, 0, st>>>(src, (double*)dst, n);
     else k_cast<float><<<flat_grid(n, 256), 256, 0, st>>>(src, (float*)dst, n);
 }
-void launch_cast_pad(int prec, const double* src, int64_t rows, int64_t cols, void* dst,
-                     int64_t ld, hipStream_t st) {
+void launch_cast_pad(int prec, const void* src, int src_dtype, int64_t lds, int64_t rows, int64_t cols,
+                     void* dst, int64_t ld, hipStream_t st) {
     if (rows <= 0) return;
-    if (prec == 0) k_cast_pad<double><<<flat_grid(rows * ld, 256), 256, 0, st>>>(src, rows, cols, (double*)dst, ld);
-    else k_cast_pad<float><<<flat_grid(rows * ld, 256), 256, 0, st>>>(src, rows, cols, (float*)dst, ld);
+    const unsigned g = flat_grid(rows * ld, 256);
+    if (src_dtype == 0) {
+        const double* s = (const double*)src;
+        if (prec == 0) k_cast_pad<double, double><<<g, 256, 0, st>>>(s, lds, rows, cols, (double*)dst, ld);
+        else k_cast_pad<double, float><<<g, 256, 0, st>>>(s, lds, rows, cols, (float*)dst, ld);
+    } else {
+        const float* s = (const float*)src;
+        if (prec == 0) k_cast_pad<float, double><<<g, 256, 0, st>>>(s, lds, rows, cols, (double*)dst, ld);
+        else k_cast_pad<float, float><<<g, 256, 0, st>>>(s, lds, rows, cols, (float*)dst, ld);
+    }
 }
-void launch_cast_transpose(int prec, const double* src, int64_t rows, int64_t cols, void* dst,
-                           int64_t ldt, int64_t r0, hipStream_t st) {
+void launch_cast_transpose(int prec, const void* src, int src_dtype, int64_t lds, int64_t rows,
+                           int64_t cols, void* dst, int64_t ldt, int64_t r0, hipStream_t st) {
     if (rows <= 0 || cols <= 0) return;
     dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
-    if (prec == 0) k_cast_transpose<double><<<grid, 256, 0, st>>>(src, rows, cols, (double*)dst, ldt, r0);
-    else k_cast_transpose<float><<<grid, 256, 0, st>>>(src, rows, cols, (float*)dst, ldt, r0);
+    if (src_dtype == 0) {
+        const double* s = (const double*)src;
+        if (prec == 0) k_cast_transpose<double, double><<<grid, 256, 0, st>>>(s, lds, rows, cols, (double*)dst, ldt, r0);
+        else k_cast_transpose<double, float><<<grid, 256, 0, st>>>(s, lds, rows, cols, (float*)dst, ldt, r0);
+    } else {
+        const float* s = (const float*)src;
+        if (prec == 0) k_cast_transpose<float, double><<<grid, 256, 0, st>>>(s, lds, rows, cols, (double*)dst, ldt, r0);
+        else k_cast_transpose<float, float><<<grid, 256, 0, st>>>(s, lds, rows, cols, (float*)dst, ldt, r0);
+    }
+}
+
+int fail(int code, const char* fmt, ...);
+
+// Output of k_dense_rowsq: a fixed device array (no allocation call), one
+// user at a time per process (the mutex), addressed through
+// hipGetSymbolAddress on the current device.
+namespace {
+constexpr int64_t ROWSQ_CHUNK = 65536;
+__device__ double g_rowsq[ROWSQ_CHUNK];
+__device__ int g_rowsq_bad;
+std::mutex g_rowsq_mu;
+}  // namespace
+
+int dense_frob2_device(const void* a, int dtype, int64_t rows, int64_t cols, int64_t lda, double* frob2) {
+    std::lock_guard<std::mutex> lock(g_rowsq_mu);
+    double* out = nullptr;
+    int* bad = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&out, HIP_SYMBOL(g_rowsq));
+    if (e == hipSuccess) e = hipGetSymbolAddress((void**)&bad, HIP_SYMBOL(g_rowsq_bad));
+    if (e != hipSuccess) return fail(CGS_EHIP, "hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+    std::vector<double> host((size_t)std::min<int64_t>(rows, ROWSQ_CHUNK));
+    int flag = 0;
+    e = hipMemcpy(bad, &flag, sizeof(int), hipMemcpyHostToDevice);
+    double s = 0.0;
+    for (int64_t r0 = 0; e == hipSuccess && r0 < rows; r0 += ROWSQ_CHUNK) {
+        const int64_t nr = std::min(ROWSQ_CHUNK, rows - r0);
+        const unsigned g = (unsigned)((nr + 255) / 256);
+        if (dtype == 0) k_dense_rowsq<double><<<g, 256, 0, 0>>>((const double*)a, lda, r0, nr, cols, out, bad);
+        else k_dense_rowsq<float><<<g, 256, 0, 0>>>((const float*)a, lda, r0, nr, cols, out, bad);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpy(host.data(), out, (size_t)nr * sizeof(double), hipMemcpyDeviceToHost);
+        for (int64_t i = 0; e == hipSuccess && i < nr; ++i) s += host[(size_t)i];
+    }
+    if (e == hipSuccess) e = hipMemcpy(&flag, bad, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(CGS_EHIP, "dense block check failed: %s", hipGetErrorString(e));
+    if (flag) return fail(CGS_EINVAL, "the dense block has a non-finite entry");
+    *frob2 = s;
+    return CGS_OK;
 }
 void launch_cast_back(int prec, const void* src, double* dst, int64_t n, hipStream_t st) {
     if (n <= 0) return;

@@ -144,12 +144,18 @@ void launch_extract(int prec, const InstDesc* inst_dev, int inst, int what, int6
                     int64_t len, double* out64, hipStream_t st);
 // generic conversion of a contiguous FP64 buffer into the working precision
 void launch_cast(int prec, const double* src, void* dst, int64_t n, hipStream_t st);
-// dst (rows x ld, working precision) <- src (rows x cols FP64, row-major), zero pad
-void launch_cast_pad(int prec, const double* src, int64_t rows, int64_t cols, void* dst,
-                     int64_t ld, hipStream_t st);
-// dst^T: dst[c * ldt + r0 + r] <- src[r * cols + c] (rows of a chunk)
-void launch_cast_transpose(int prec, const double* src, int64_t rows, int64_t cols, void* dst,
-                           int64_t ldt, int64_t r0, hipStream_t st);
+// dst (rows x ld, working precision) <- src (rows x cols, row stride lds,
+// FP64 when src_dtype = 0, FP32 when 1), zero pad
+void launch_cast_pad(int prec, const void* src, int src_dtype, int64_t lds, int64_t rows, int64_t cols,
+                     void* dst, int64_t ld, hipStream_t st);
+// dst^T: dst[c * ldt + r0 + r] <- src[r * lds + c] (rows of a chunk)
+void launch_cast_transpose(int prec, const void* src, int src_dtype, int64_t lds, int64_t rows,
+                           int64_t cols, void* dst, int64_t ldt, int64_t r0, hipStream_t st);
+// Sum of squares of a device matrix (rows x cols, row stride lda, FP64 when
+// dtype = 0, FP32 when 1), in the order the host forms it for a copied block:
+// each row's squares summed in column order, then the row sums in row order.
+// Returns CGS_OK, CGS_EINVAL when an entry is not finite, CGS_EHIP.
+int dense_frob2_device(const void* a, int dtype, int64_t rows, int64_t cols, int64_t lda, double* frob2);
 // dst (FP64) <- src (working precision)
 void launch_cast_back(int prec, const void* src, double* dst, int64_t n, hipStream_t st);
 // out[i * NSC + j] = scalar j of instance i

@@ -38,6 +38,14 @@ class ConeProblem:
     n_signal: int        # length of the natural variable x inside z
 
 
+def _is_device_tensor(a) -> bool:
+    try:
+        import torch
+    except ImportError:   # pragma: no cover
+        return False
+    return isinstance(a, torch.Tensor) and a.is_cuda
+
+
 def deconv_problem(taps, b_obs) -> ConeProblem:
     taps = np.asarray(taps, dtype=np.float64)
     b_obs = np.asarray(b_obs, dtype=np.float64)
@@ -57,7 +65,9 @@ def deconv_problem(taps, b_obs) -> ConeProblem:
 
 
 def lasso_problem(A, b_obs, lam: float) -> ConeProblem:
-    A = np.asarray(A, dtype=np.float64)
+    # (a torch tensor on the GPU is passed through: the operator borrows it)
+    if not _is_device_tensor(A):
+        A = np.asarray(A, dtype=np.float64)
     b_obs = np.asarray(b_obs, dtype=np.float64)
     m0, n0 = A.shape
     nv = 2 * n0 + 1

@@ -163,3 +163,28 @@ def test_library_equilibration_matches_oracle():
             np.testing.assert_allclose(sig, (ref.sigma_b, ref.sigma_c), rtol=1e-12)
             if level == 1:
                 assert np.all(d == 1.0) and np.all(e == 1.0)
+
+
+def test_typed_dense_blocks():
+    """cgs_op_add_dense_ex: unknown dtype or memory kind and non-finite entries
+    are rejected; an FP32 host block is widened exactly, so the operator (its
+    norms, hence its scaling) equals the FP64 copy of the same values."""
+    lib = P.lib()
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((7, 5)).astype(np.float32)
+    op = P.Operator(9, 6)
+    assert lib.cgs_op_add_dense_ex(op._h, 0, 0, 2, 2, A.ctypes.data, 5, 7, P.MEM_HOST_COPY, 1.0) == -1
+    assert lib.cgs_op_add_dense_ex(op._h, 0, 0, 2, 2, A.ctypes.data, 5, P.DTYPE_F32, 5, 1.0) == -1
+    assert lib.cgs_op_add_dense_ex(op._h, 0, 0, 2, 2, None, 5, P.DTYPE_F32, P.MEM_HOST_COPY, 1.0) == -1
+    assert lib.cgs_op_add_dense_ex(op._h, 0, 0, 2, 6, A.ctypes.data, 5, P.DTYPE_F32, P.MEM_HOST_COPY, 1.0) == -2
+    bad = A.copy()
+    bad[2, 3] = np.inf
+    with pytest.raises(P.CgsError) as e:
+        P.Operator(9, 6).add_dense(1, 0, bad)
+    assert e.value.code == -1
+    op64 = P.Operator(9, 6).add_dense(1, 0, A.astype(np.float64), scale=0.5)
+    op32 = P.Operator(9, 6).add_dense(1, 0, A, scale=0.5)
+    for level in (1, 2):
+        d64, e64, _ = op64.equilibrate(9, [], level=level)
+        d32, e32, _ = op32.equilibrate(9, [], level=level)
+        assert np.array_equal(d64, d32) and np.array_equal(e64, e32)

@@ -605,6 +605,50 @@ def test_bf16_batch_solve_matches_oracle():
         assert abs(f - fr) / abs(fr) <= 1e-4, (i, f, fr)
 
 
+@pytest.mark.parametrize("prec,tdtype", [(P.FP32, "float32"), (P.FP64, "float64"), (P.BF16, "float32")],
+                         ids=["fp32", "fp64", "bf16"])
+def test_borrowed_dense_block_equals_host_copy(prec, tdtype):
+    """A dense block read in place from a torch tensor on the GPU (never copied
+    to the host) gives the same solve, bit for bit, as the same values copied
+    from host FP64 memory: the block's norm (the scaling) and its conversion to
+    the working precision are formed in the same order.  The solution also
+    meets the oracle's residual test."""
+    import torch
+    _say("borrowed dense block", prec, tdtype)
+    B = 4 if prec == P.BF16 else 1
+    A, prs, progs = _lasso_batch(250, 600, B, 47)
+    if tdtype == "float32":
+        A = A.astype(np.float32).astype(np.float64)   # values an FP32 tensor holds exactly
+    At = torch.tensor(A, dtype=getattr(torch, tdtype), device="cuda")
+    out = []
+    for a in (A, At):
+        ps = [P.lasso_problem(a, pr.b[2 * 600 + 1:-1] / -2.0, float(pr.c[600])) for pr in prs]
+        s = _solver(ps[0], prec, batch=B, eps=BF16_EPS if prec == P.BF16 else 1e-5, check_every=10,
+                    normalize=2)
+        for i, p_ in enumerate(ps):
+            s.set_data(i, p_.b, p_.c)
+        infos = s.solve()
+        out.append([(inf["iters"], s.solution(i)) for i, inf in enumerate(infos)])
+        del s
+    for i in range(B):
+        (it_h, (xh, yh, sh)), (it_d, (xd, yd, sd)) = out[0][i], out[1][i]
+        assert it_h == it_d
+        assert np.array_equal(xh, xd) and np.array_equal(yh, yd) and np.array_equal(sh, sd)
+        prog = o.lasso_program(A, prs[i].b[2 * 600 + 1:-1] / -2.0, float(prs[i].c[600]))
+        rp, rd, gap, _, _ = o.scs.residuals(prog, xd, yd, 1.0, sd)
+        assert max(rp, rd, gap) <= 1e-4, (i, rp, rd, gap)
+
+
+def test_borrowed_dense_block_must_be_device_memory():
+    """A host pointer (or a device pointer of another kind) is refused with
+    CGS_EINVAL instead of being dereferenced on the device."""
+    lib = P.lib()
+    A = np.ones((4, 3), dtype=np.float32)
+    op = P.Operator(4, 3)
+    assert lib.cgs_op_add_dense_ex(op._h, 0, 0, 4, 3, A.ctypes.data, 3, P.DTYPE_F32,
+                                   P.MEM_DEVICE_BORROW, 1.0) == -1
+
+
 # ----------------------------------------------------------------- autotuner
 
 def test_autotune_keeps_results_within_bounds():
