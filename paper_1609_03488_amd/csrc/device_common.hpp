@@ -146,31 +146,6 @@ DEVI double sum_parts(const double* part, int t0, int t1, int j, double* sh) {
     return block_sum<NT>(s, sh);
 }
 
-// sum_parts returned to every thread.
-template <int NT>
-DEVI double sum_parts_all(const double* part, int t0, int t1, int j, double* sh) {
-    const double s = sum_parts<NT>(part, t0, t1, j, sh);
-    __syncthreads();
-    if (threadIdx.x == 0) sh[0] = s;
-    __syncthreads();
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
-// Fixed-order sum of the instance's X-tile partials (slot j) of the previous
-// kernel, returned to every thread: each workgroup of a consumer kernel
-// recomputes the same value, so no separate one-workgroup kernel is needed.
-DEVI double inst_xsum(const Tables& tb, const InstDesc& d, int j, double* sh) {
-    const double s = sum_parts<VEC_NT>(tb.xpart, d.xt0, d.xt1, j, sh);
-    __syncthreads();
-    if (threadIdx.x == 0) sh[0] = s;
-    __syncthreads();
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-
 // All four X-tile partial slots of the instance at once (sh: 4 * VEC_NT / 64).
 DEVI void inst_xsum4(const Tables& tb, const InstDesc& d, double (&s)[4], double* sh) {
 #pragma unroll
@@ -232,17 +207,6 @@ DEVI double cg_tolerance(double k, double hh, double zeta, double rate, double f
     double rel = zeta > 0.0 ? zeta / pow(k + 1.0, rate) : 0.0;
     rel = rel > floor_ ? rel : floor_;
     return sqrt(hh) * rel;
-}
-
-// The same for the instance's Y-tile partials.
-DEVI double inst_ysum(const Tables& tb, const InstDesc& d, int j, double* sh) {
-    const double s = sum_parts<VEC_NT>(tb.ypart, d.yt0, d.yt1, j, sh);
-    __syncthreads();
-    if (threadIdx.x == 0) sh[0] = s;
-    __syncthreads();
-    const double r = sh[0];
-    __syncthreads();
-    return r;
 }
 
 // Tile of a kernel that walks the X tiles and then the Y tiles.

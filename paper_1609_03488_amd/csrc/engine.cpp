@@ -840,11 +840,11 @@ void Engine::admm_step() {
     }
     if (folded_cg()) {
         // z_y, the tau products and the cone terms came from the last CG update
-        launch_project(prec, T, st.alpha, stream, 1);            // relax, project, dual update
+        launch_project(prec, T, st.alpha, stream);               // relax, project, dual update
         return;
     }
-    launch_tau_dots(prec, T, st.alpha, 1, stream);               // z_y = w_y + A z; c^T z_x + b^T z_y
-    launch_soc_prep(prec, T, st.alpha, stream);                  // SOC norms of u_bar - v
+    // z_y = w_y + A z; c^T z_x + b^T z_y; the cone terms of u_bar - v (CgStart::cone)
+    launch_tau_dots(prec, T, st.alpha, stream);
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
 }
 

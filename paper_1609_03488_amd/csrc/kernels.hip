@@ -356,29 +356,6 @@ DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<c
     }
 }
 
-template <typename T>
-DEVI void tau_tile(const Tables& tb, const InstDesc& d, const XYTile& xt, double* sh) {
-    gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
-    double s0 = 0.0;
-    if (xt.is_y) {
-        gptr<const T> wy = yvec<T>(d, YW);
-        gptr<const T> az = yvec<T>(d, YA);
-        gptr<T> zy = yvec<T>(d, YZ);
-        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT) {
-            const T v = (T)((double)wy[i] + (double)az[i]);
-            zy[i] = v;
-            s0 = fma((double)a[i], (double)v, s0);
-        }
-    } else {
-        gptr<const T> zx = xvec<T>(d, XZ);
-        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
-            s0 = fma((double)a[i], (double)zx[i], s0);
-    }
-    s0 = block_sum<VEC_NT>(s0, sh);
-    double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
-    if (threadIdx.x == 0) part[0] = s0;
-}
-
 // One CG step after the products: alpha = ||r||^2 / <p, q>; z += alpha p;
 // r' = r - alpha q (and the carried K z, A z when tracking); then the next
 // direction p = r' + beta p in the same pass.  beta needs ||r'||^2 before r'
@@ -466,37 +443,22 @@ __global__ __launch_bounds__(VEC_NT) void k_wy(Tables tb, int gate) {
         w[i] = (T)((double)u[i] + (double)v[i]);
 }
 
-// u~_tau = (w_tau + c^T z_x + b^T z_y) / eta  (exact solve of (I+Q) u~ = w,
-// last row), then the tau/kappa part of relaxation, projection and dual update.
-// With `form_zy`, the Y tiles first form z_y = w_y + A z from the carried A z.
+// The products of u~_tau = (w_tau + c^T z_x + b^T z_y) / eta (exact solve of
+// (I+Q) u~ = w, last row) after CG, on the one-launch-per-kernel path: z_y =
+// w_y + (carried A z), the partials of c^T z_x and b^T z_y, and the cone terms
+// of the projection (the work the update that ends CG does on the folded path,
+// with z and A z as CG left them; CgStart::cone)
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha, int form_zy) {
-    __shared__ double sh[VEC_NT / 64];
+__global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha) {
+    __shared__ double sh[4 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
     gptr<double> sc = scal(d);
     if (!gate_ok(sc, G_ADMM)) return;
-    if (form_zy) {
-        tau_tile<T>(tb, d, xt, sh);
-        return;
-    }
-    gptr<const T> a = xt.is_y ? yvec<T>(d, YB) : xvec<T>(d, XC);
-    gptr<T> b = xt.is_y ? yvec<T>(d, YZ) : xvec<T>(d, XZ);
-    double s0 = 0.0;
-    {
-        for (int64_t i = xt.t.start + threadIdx.x; i < xt.t.start + xt.t.len; i += VEC_NT)
-            s0 = fma((double)a[i], (double)b[i], s0);
-    }
-    s0 = block_sum<VEC_NT>(s0, sh);
-    double* part = (xt.is_y ? tb.ypart : tb.xpart) + 4 * (int64_t)xt.index;
-    if (threadIdx.x == 0) part[0] = s0;
+    const CgStart cs{0.0, 0.0, 0.0, 0, 1, 1, alpha};
+    cg_elems<T>(tb, d, xt, sc, cs, false, 0.0, 0.0, false, false, true, XZ, XR, XP, XQ, sh);
 }
 
-// u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta from k_tau_dots' partials
-// (slot 0), recomputed by every workgroup; the first Y tile's workgroup keeps
-// it for the projection.  Tiles of a second-order cone then store the cone's
-// head value (u_bar - v at its first row) and partial sums of squares of the
-// tail (Y partial slot 1).
 // A thread's elements of a Y tile of u_y, z_y, g_y, v_s, loaded at once
 // (ahead of a reduction, and ahead of stores into the same vectors, which
 // element by element would order each load after the previous stores);
@@ -528,34 +490,7 @@ struct YbarTile {
 };
 
 template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_soc_prep(Tables tb, double alpha) {
-    __shared__ double sh[VEC_NT / 64];
-    const VecTile tl = tb.yt[blockIdx.x];
-    const InstDesc d = tb.inst[tl.inst];
-    gptr<double> sc = scal(d);
-    if (!gate_ok(sc, G_ADMM)) return;
-    YbarTile<T> yb;
-    if (tl.seg >= 0) yb.load(d, tl);   // (in flight during the sums)
-    const double x0 = inst_xsum(tb, d, 0, sh);
-    const double y0 = inst_ysum(tb, d, 0, sh);
-    const double ut = (sc[SC_TAU] + sc[SC_KAPPA] + x0 + y0) / sc[SC_ETA];
-    if ((int)blockIdx.x == d.yt0 && threadIdx.x == 0) sc[SC_UT] = ut;
-    if (tl.seg < 0) return;
-    const SocSeg sg = tb.seg[tl.seg];
-    double s0 = 0.0;
-#pragma unroll
-    for (int j = 0; j < YbarTile<T>::R; ++j) {
-        if (!yb.has(tl, j)) continue;
-        const double pv = yb.pv(j, ut, alpha);
-        if (yb.at(tl, j) == sg.start) tb.seg_val[2 * tl.seg] = pv;
-        else s0 = fma(pv, pv, s0);
-    }
-    s0 = block_sum<VEC_NT>(s0, sh);
-    if (threadIdx.x == 0) tb.ypart[4 * (int64_t)blockIdx.x + 1] = s0;
-}
-
-template <typename T>
-__global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha, int cone) {
+__global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha) {
     __shared__ double sh[4 * (VEC_NT / 64)];
     const XYTile xt = xy_tile(tb);
     const InstDesc d = tb.inst[xt.t.inst];
@@ -563,9 +498,8 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha, int
     if (!gate_ok(sc, G_ADMM)) return;
     const int seg = xt.is_y ? xt.t.seg : -1;
     YbarTile<T> yb;
-    if (seg >= 0 && !cone) yb.load(d, xt.t);   // (in flight during the sums)
     double ut, t = 0.0, nz = 0.0;
-    if (cone) {
+    {
         // u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta from the slot-0
         // partials (Tables::tpart) of every X and Y tile of the instance, and the cone's head
         // value and tail norm from the cone terms (CgStart::cone), all summed
@@ -593,17 +527,10 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha, int
             const double n2 = s[1] - 2.0 * dl * s[2] + dl * dl * s[3];
             nz = sqrt(n2 > 0.0 ? n2 : 0.0);
         }
-    } else {
-        ut = sc[SC_UT];
-        if (seg >= 0) {
-            const SocSeg sg = tb.seg[seg];
-            t = tb.seg_val[2 * seg];
-            nz = sqrt(sum_parts_all<VEC_NT>(tb.ypart, sg.yt0, sg.yt0 + sg.ntiles, 1, sh));
-        }
     }
     if (!xt.is_y && xt.index == d.xt0 && threadIdx.x == 0) {
         // tau, kappa of the step (no other workgroup of this kernel reads them)
-        if (cone) sc[SC_UT] = ut;
+        sc[SC_UT] = ut;
         const double tau = sc[SC_TAU], kap = sc[SC_KAPPA];
         const double ubar = alpha * ut + (1.0 - alpha) * tau;
         const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
@@ -638,7 +565,7 @@ __global__ __launch_bounds__(VEC_NT) void k_project(Tables tb, double alpha, int
         return;
     }
     const SocSeg sg = tb.seg[seg];
-    if (cone) yb.load(d, xt.t);
+    yb.load(d, xt.t);
     // Pi(t, z): (t, z) if ||z|| <= t; 0 if ||z|| <= -t; ((t+||z||)/2)(1, z/||z||) otherwise
     int mode;
     double a = 0.0;
@@ -1098,15 +1025,11 @@ void launch_snapshot(int prec, const Tables& t, int restore, hipStream_t st) {
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_wy, t.ny_tiles, VEC_NT, st, t, gate);
 }
-void launch_tau_dots(int prec, const Tables& t, double alpha, int form_zy, hipStream_t st) {
-    CGS_DISPATCH(prec, k_tau_dots, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha, form_zy);
+void launch_tau_dots(int prec, const Tables& t, double alpha, hipStream_t st) {
+    CGS_DISPATCH(prec, k_tau_dots, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
 }
-void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st) {
-    // every Y tile: u~_tau for all instances, cone partials where there are cones
-    CGS_DISPATCH(prec, k_soc_prep, t.ny_tiles, VEC_NT, st, t, alpha);
-}
-void launch_project(int prec, const Tables& t, double alpha, hipStream_t st, int cone) {
-    CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha, cone);
+void launch_project(int prec, const Tables& t, double alpha, hipStream_t st) {
+    CGS_DISPATCH(prec, k_project, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, alpha);
 }
 void launch_resid(int prec, const Tables& t, double eps, int max_iters, int gate, hipStream_t st) {
     CGS_DISPATCH(prec, k_resid, t.nx_tiles + t.ny_tiles, VEC_NT, st, t, eps, max_iters, gate);

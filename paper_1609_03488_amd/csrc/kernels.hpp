@@ -85,11 +85,11 @@ struct CgStart {
     double zeta, rate, floor_;
     int on;
     // 1: the update in which an instance's CG ends also does the work of
-    // launch_tau_dots (form_zy = 1) on the final z and A z (folded ADMM path,
+    // launch_tau_dots on the final z and A z (folded ADMM path,
     // where some update of the loop always runs)
     int tau;
     // with tau: that update also forms the cone terms of the projection that
-    // follows (launch_project with cone = 1; no launch_soc_prep): relative to
+    // follows (launch_project): relative to
     // the expansion point e = the previous step's u~_tau, every second-order
     // cone row has u_bar - v = a - (u~_tau - e) b with
     //   a = alpha z_y + (1 - alpha) u_y - v_s - alpha e g_y,   b = alpha g_y,
@@ -115,16 +115,14 @@ void launch_snapshot(int prec, const Tables& t, int restore, hipStream_t st);
 // ---- ADMM step pieces (Section V-B: subspace projection, then cone projection)
 // w_y = u_y + v_s
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st);
-// u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta, then tau, kappa updates
-// form_zy = 1: z_y = w_y + (carried A z) is formed in the same pass
-void launch_tau_dots(int prec, const Tables& t, double alpha, int form_zy, hipStream_t st);
-// head value and tail sum of squares of (u_bar_y - v_s) per second-order cone
-void launch_soc_prep(int prec, const Tables& t, double alpha, hipStream_t st);
-// relaxation, projection onto K, dual update of every X/Y entry.  cone = 0:
-// u~_tau and the cone norms come from launch_soc_prep; cone = 1: every
-// workgroup forms u~_tau from the tau products' partials and the cone norms
-// from the cone terms of the update that ended CG (CgStart::cone)
-void launch_project(int prec, const Tables& t, double alpha, hipStream_t st, int cone = 0);
+// after CG on the one-launch-per-kernel path: z_y = w_y + (carried A z), the
+// partials of c^T z_x and b^T z_y and the cone terms of CgStart::cone (the
+// work the update that ends CG does on the folded path)
+void launch_tau_dots(int prec, const Tables& t, double alpha, hipStream_t st);
+// relaxation, projection onto K, dual update of every X/Y entry: every
+// workgroup forms u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta from the tau
+// products' partials and the cone norms from the cone terms (CgStart::cone)
+void launch_project(int prec, const Tables& t, double alpha, hipStream_t st);
 // termination quantities from A u_x (in YT) and A^T u_y (in XT)
 void launch_resid(int prec, const Tables& t, double eps, int max_iters, int gate, hipStream_t st);
 
