@@ -177,15 +177,36 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
     __shared__ cf tw[TW_N];
     __shared__ double red[4 * (FT / 64)];
     Fold4 f{0.0, 0.0, 0.0, 0.0};
-    if ((int)blockIdx.x >= cl.nftiles) {   // initialisation tiles riding on the launch
-        const VecTile it = cl.init[blockIdx.x - cl.nftiles];
+    int bid = (int)blockIdx.x;
+    if (FOLD == 0 && cl.pair) {
+        // two applies in one launch: the second operand set's transform
+        // workgroups follow the first set's, then both sets' initialisation
+        // tiles in the same order
+        bool second;
+        if (bid < 2 * cl.nftiles) {
+            second = bid >= cl.nftiles;
+            bid -= second ? cl.nftiles : 0;
+        } else {
+            int w = bid - 2 * cl.nftiles;
+            second = w >= cl.ninit;
+            w -= second ? cl.ninit : 0;
+            bid = cl.nftiles + w;
+        }
+        if (second) {
+            out = cl.out2;
+            in = cl.in2;
+            base = cl.base2;
+        }
+    }
+    if (bid >= cl.nftiles) {   // initialisation tiles riding on the launch
+        const VecTile it = cl.init[bid - cl.nftiles];
         const InstDesc di = tb.inst[it.inst];
         if (!gate_ok(scal(di), gate)) return;
         init_tile<float, false>(tb, di, it, adj, out, in, base, sigma, FOLD, cl.fr, cl.fp, cl.fq, f);
         if (FOLD) fold_partials(cl.part, f, red);
         return;
     }
-    const ConvTile tl = cl.ftiles[blockIdx.x];
+    const ConvTile tl = cl.ftiles[bid];
     const InstDesc d = tb.inst[tl.inst];
     const ConvBlock cb = cl.blocks[tl.blk];   // (loaded beside the instance, ahead of the gate)
     if (!gate_ok(scal(d), gate)) return;
@@ -397,7 +418,7 @@ void launch_conv_spectrum(const void* w, int64_t k, void* spec, hipStream_t st) 
 
 void launch_conv_fft(const Tables& t, const ConvLaunch& c, int adj, int out, int in, int base, double sigma,
                      int gate, hipStream_t st) {
-    const int grid = c.nftiles + c.ninit;
+    const int grid = (c.nftiles + c.ninit) * (c.pair && c.fold == 0 ? 2 : 1);
     if (grid <= 0) return;
     if (c.fold == 1) k_conv_fft<1><<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);
     else if (c.fold == 2) k_conv_fft<2><<<grid, FT, 0, st>>>(t, c, adj, out, in, base, sigma, gate);

@@ -848,14 +848,37 @@ void Engine::admm_step() {
     launch_project(prec, T, st.alpha, stream);                   // relax, project, dual update
 }
 
+// Two applies of one direction; one launch where the FFT engine alone serves
+// that direction (its transform workgroups and initialisation tiles for both).
+void Engine::apply_pair(int adj, int out1, int in1, int base1, int out2, int in2, int base2, double sigma,
+                        int gate) {
+    const auto& cl = adj ? ca : cf;
+    if (prec == 1 && st.conv_mfma == 2 && fold_init[adj] && cl.size() == 1 && cl[0].fft &&
+        (adj ? da : df).empty() && !use_gemm) {
+        ConvLaunch c = cl[0];
+        c.pair = 1;
+        c.out2 = out2;
+        c.in2 = in2;
+        c.base2 = base2;
+        launch_conv_fft(T, c, adj, out1, in1, base1, sigma, gate, stream);
+        return;
+    }
+    apply(adj, out1, in1, base1, sigma, gate);
+    apply(adj, out2, in2, base2, sigma, gate);
+}
+
 void Engine::check(int gate) {
+    if (gate == G_CHECK) {
+        // with the exact A z and z + A^T A z for the next interval (the gates
+        // G_CHECK and G_ADMM select the same instances)
+        apply_pair(0, YT, XU, -1, YA, XZ, -1, 1.0, gate);       // A u_x, A z
+        apply_pair(1, XT, YU, -1, XK, YA, XZ, 1.0, gate);       // A^T u_y, z + A^T A z
+        launch_resid(prec, T, st.eps, st.max_iters, gate, stream);
+        return;
+    }
     apply(0, YT, XU, -1, 1.0, gate);                             // A u_x
     apply(1, XT, YU, -1, 1.0, gate);                             // A^T u_y
     launch_resid(prec, T, st.eps, st.max_iters, gate, stream);
-    if (gate == G_CHECK) {
-        apply(0, YA, XZ, -1, 1.0, G_ADMM);                       // exact A z
-        apply(1, XK, YA, XZ, 1.0, G_ADMM);                       // and z + A^T A z
-    }
 }
 
 // Exact recomputation of the carried products of the CG warm start.

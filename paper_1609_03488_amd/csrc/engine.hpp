@@ -255,6 +255,8 @@ class Engine {
     // nsteps ADMM steps with the termination test after every check_every of them
     void steps_with_checks(int nsteps);
     void check(int gate = G_CHECK);
+    void apply_pair(int adj, int out1, int in1, int base1, int out2, int in2, int base2, double sigma,
+                    int gate);
     void refresh();
     void adapt_cg();
     // ---- host loops

@@ -36,6 +36,10 @@ struct ConvLaunch {
     int fold;
     int fr, fp, fq, fit;
     double* part;
+    // FFT engine, fold = 0: pair = 1 runs a second apply of the same direction
+    // in the same launch, on kinds (out2, in2, base2) with the same sigma
+    int pair;
+    int out2, in2, base2;
 };
 // dynamic LDS bytes of the convolution kernel for a staging pass of kc taps
 size_t conv_smem_bytes(int prec, int kc);
