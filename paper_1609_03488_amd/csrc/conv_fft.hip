@@ -247,20 +247,23 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
     }
     fill_twiddles(tw);
     fft2048(v, lds, tw);
-    // product with conj(DFT(w)), conjugated: the inverse is a forward transform
+    // product with conj(DFT(w)), conjugated: the inverse is a forward transform.
+    // The thread holds X[t + 256 (h + 2 r)] in v[4 h + r], which is exactly
+    // the set x[t + 256 r'] the next transform's first stage takes from it:
+    // the products only change register, v'[r'] = p[4 (r' % 2) + r' / 2]
+    // (no exchange through LDS; the transform ended with a barrier).
     gptr<const float> sp = (gptr<const float>)spec;   // interleaved (re, im)
+    cf pr[8];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int j = t + FT * h + 512 * r;
             const cf p = cmul(v[4 * h + r], cf{sp[2 * j], sp[2 * j + 1]});
-            lds[lp(j)] = {p.x, -p.y};
+            pr[h + 2 * r] = {p.x, -p.y};
         }
-    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = lds[lp(t + FT * r)];
-    __syncthreads();
+    for (int r = 0; r < 8; ++r) v[r] = pr[r];
     fft2048(v, lds, tw);
     // conj(result) / L: real part = window a, imaginary part = window b.
     // Epilogue: every load of the thread's outputs (base, identity blocks,
