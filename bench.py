@@ -488,7 +488,7 @@ def run_lasso_batch(args, cfg):
         s.set_data(i, pr.b, pr.c)
     tuned = None
     if not args.no_autotune:
-        tuned = s.autotune(reps=5)
+        tuned = s.autotune(reps=10)
         log(f"autotune: batched GEMM aims at {tuned['gemm_target_wgs']} workgroups, "
             f"vector tiles of {tuned['vec_tile']}")
     infos, elapsed = timed_solves(s, args.steps, args.warmup, cfg["name"])

@@ -548,6 +548,10 @@ int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice) {
     if (have_data && e.n_multi > 0) tiles = {cgs::VEC_TILE_MIN, cgs::VEC_TILE};
     else tiles = {e.vec_tile};
     int best_m = e.st.conv_mfma, best_t = e.gemm_target, best_v = e.vec_tile;
+    // BF16 products are timed with their refinement terms (the hi/lo phase,
+    // where a BF16 solve spends most of its applies)
+    const int keep_corr = e.gemm_corr;
+    if (e.use_gemm) e.gemm_corr = 1;
     if (have_data && e.n_multi > 0) {
         // every combination timed on whole ADMM steps of the solver's own
         // instances: the launches the solve runs, folded ones included
@@ -619,6 +623,7 @@ int cgs_solver_autotune(cgs_solver* s, int32_t reps, int32_t* choice) {
             e.gemm_target = best_t;
         }
     }
+    e.gemm_corr = keep_corr;
     e.drop_graph();
     if (choice) {
         choice[0] = (!e.cf.empty() && e.prec == 1) ? e.st.conv_mfma : -1;
