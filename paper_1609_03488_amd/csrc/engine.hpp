@@ -205,7 +205,7 @@ class Engine {
     uint16_t* panel = nullptr;   // three BF16 panels (hi, mid, lo) of panel_stride elements
     size_t panel_stride = 0;
     float* gemm_part = nullptr;
-    int gemm_target = 512;       // GEMM workgroups aimed for (autotuned)
+    int gemm_target = 256;       // GEMM workgroups aimed for (autotuned; 256 its usual choice)
     int vec_tile = VEC_TILE;     // elements per X/Y vector tile (autotuned)
 
     // side stream for the fused launch, overlapped with the one-launch-per-kernel
