@@ -202,7 +202,8 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         const VecTile it = cl.init[bid - cl.nftiles];
         const InstDesc di = tb.inst[it.inst];
         if (!gate_ok(scal(di), gate)) return;
-        init_tile<float, false>(tb, di, it, adj, out, in, base, sigma, FOLD, cl.fr, cl.fp, cl.fq, f);
+        init_tile<float, false>(tb, di, it, adj, out, in, base, sigma, FOLD, cl.fr, cl.fp, cl.fq, f,
+                                FOLD == 1 ? cl.idrows : 0);
         if (FOLD) fold_partials(cl.part, f, red);
         return;
     }
@@ -378,16 +379,35 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
         for (int e = 0; e < NE; ++e) kv[e] = kz[li[e] >= 0 ? li[e] : 0];
         gptr<float> rv = xvec<float>(d, cl.fr) + gw;
         gptr<float> pv = xvec<float>(d, cl.fp) + gw;
+        float rrv[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
+            rrv[e] = 0.0f;
             if (li[e] < 0) continue;
             const float hv = (float)(bv[e] + s * res[e]);
             const double hd = (double)hv;
             const float rr = (float)(hd - (double)kv[e]);
+            rrv[e] = rr;
             rv[li[e]] = rr;
             pv[li[e]] = rr;
             f.a += (double)rr * (double)rr;
             f.b += hd * hd;
+        }
+        if (cl.idrows) {
+            // A p's identity rows for p = r: A's block maps X column col0 + i
+            // to Y row row0 + i (ConvLaunch::idrows)
+            gptr<float> yt = yvec<float>(d, cl.idrows - 1);
+            for (int b = d.id0; b < d.id1; ++b) {
+                const IdBlock ib = tb.ids[b];
+                const int64_t rl = ib.col0 - gw, rh = ib.col0 + ib.len - gw;
+                if (ib.len <= 0 || rh <= 0 || rl >= 2 * (int64_t)B) continue;
+                const int lo = rl < 0 ? 0 : (int)rl;
+                const int hi = rh > 2 * (int64_t)B ? 2 * B : (int)rh;
+                gptr<float> yw = yt + (ib.row0 - ib.col0 + gw);
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+                    if (li[e] >= lo && li[e] < hi) yw[li[e]] = (float)(0.0 + ib.scale * (double)rrv[e]);
+            }
         }
     } else {
         // q = value; partials <p, q>, ||r||^2, <r, q>, ||q||^2

@@ -399,8 +399,8 @@ struct Fold4 {
 //   mode 1: h = v; r = h - x_fq, p = r are written (not h); a += r^2, b += h^2
 //   mode 2: q = v is written to `out`; a += p q, b += r^2, c += r q, d += q^2
 template <typename T>
-DEVI void fold_elem(const InstDesc& d, int mode, int fr, int fp, int fq, int out, int64_t g, double v,
-                    Fold4& f) {
+DEVI void fold_elem(const Tables& tb, const InstDesc& d, int mode, int fr, int fp, int fq, int out,
+                    int64_t g, double v, Fold4& f, int idrows) {
     if (mode == 1) {
         const T h = (T)v;
         const double hd = (double)h;
@@ -409,6 +409,14 @@ DEVI void fold_elem(const InstDesc& d, int mode, int fr, int fp, int fq, int out
         xvec<T>(d, fp)[g] = r;
         f.a += (double)r * (double)r;
         f.b += hd * hd;
+        if (idrows) {
+            // A p's identity rows for p = r (ConvLaunch::idrows)
+            for (int b = d.id0; b < d.id1; ++b) {
+                const IdBlock ib = tb.ids[b];
+                if (g >= ib.col0 && g < ib.col0 + ib.len)
+                    yvec<T>(d, idrows - 1)[ib.row0 + g - ib.col0] = (T)(0.0 + ib.scale * (double)r);
+            }
+        }
     } else {
         const T q = (T)v;
         xvec<T>(d, out)[g] = q;
@@ -425,7 +433,7 @@ DEVI void fold_elem(const InstDesc& d, int mode, int fr, int fp, int fq, int out
 // the batched loop's code and registers would cost the kernel's main path.
 template <typename T, bool BATCH = true>
 DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int adj, int out, int in,
-                    int base, double sigma, int fold, int fr, int fp, int fq, Fold4& f) {
+                    int base, double sigma, int fold, int fr, int fp, int fq, Fold4& f, int idrows = 0) {
     gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
     gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
     gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
@@ -480,7 +488,7 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
                 const int64_t c0 = adj ? ib.row0 : ib.col0;
                 if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
             }
-            if (fold) fold_elem<T>(d, fold, fr, fp, fq, out, i, v, f);
+            if (fold) fold_elem<T>(tb, d, fold, fr, fp, fq, out, i, v, f, idrows);
             else o[i] = (T)v;
         }
         return;
@@ -514,7 +522,7 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
 #pragma unroll
             for (int j = 0; j < IB; ++j)
                 if (j < nb && i >= br0[j] && i < bhi[j]) v += bw[j] * (double)sv[j][u];
-            if (fold) fold_elem<T>(d, fold, fr, fp, fq, out, i, v, f);
+            if (fold) fold_elem<T>(tb, d, fold, fr, fp, fq, out, i, v, f, idrows);
             else o[i] = (T)v;
         }
     }

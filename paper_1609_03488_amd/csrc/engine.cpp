@@ -614,6 +614,31 @@ int Engine::build(const std::vector<InstRec>& r) {
         for (const ConvTile& t : im.cadj[0]) fft = fft && im.cblk[t.blk].k <= FFT_KMAX;
         fold_cg = fft && !im.fadj.empty() ? 1 : 0;
     }
+    // The right-hand side launch can also write the identity rows of A p (the
+    // first CG product, p = r): possible when, in every instance on this
+    // path, the convolution rows and rows reached by exactly one identity
+    // block cover the Y vector; the step's first A p launch then needs no
+    // initialisation workgroups.
+    idrows = 0;
+    if (fold_cg) {
+        bool ok = true;
+        for (const InstDesc& d : im.inst) {
+            if (d.fused) continue;
+            std::vector<std::pair<int64_t, int64_t>> iv;
+            for (int b = d.cb0; b < d.cb1; ++b)
+                iv.emplace_back(im.cblk[b].row0, im.cblk[b].row0 + im.cblk[b].n_in + im.cblk[b].k - 1);
+            for (int b = d.id0; b < d.id1; ++b)
+                if (im.ids[b].len > 0) iv.emplace_back(im.ids[b].row0, im.ids[b].row0 + im.ids[b].len);
+            std::sort(iv.begin(), iv.end());
+            int64_t pos = 0;
+            for (const auto& r : iv) {
+                ok = ok && r.first == pos;
+                pos = r.second;
+            }
+            ok = ok && pos == d.m && d.db0 == d.db1;
+        }
+        idrows = ok ? 1 : 0;
+    }
     for (InstDesc& d : im.inst) d.cp0 = d.cp1 = d.ip0 = d.ip1 = 0;
     if (fold_cg) {
         const int nft = (int)im.fadj[0].size();
@@ -777,7 +802,15 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         // whatever the CG start test says (a step without CG iterations is
         // rare) and the update evaluates the test from the right-hand side's
         // partials, so no launch separates the right-hand side from A p
-        apply(0, YT, XP, -1, 1.0, G_ADMM);
+        if (idrows) {
+            // (the identity rows of A p came with p from the right-hand side launch)
+            for (ConvLaunch a : cf) {
+                a.ninit = 0;
+                conv(a, 0, YT, XP, -1, 1.0, G_ADMM);
+            }
+        } else {
+            apply(0, YT, XP, -1, 1.0, G_ADMM);
+        }
         ConvLaunch c = ca[0];
         c.fold = 2;
         c.fr = XR;
@@ -827,6 +860,7 @@ void Engine::admm_step() {
         c.fp = XP;
         c.fq = XK;
         c.part = T.spart;
+        c.idrows = idrows ? YT + 1 : 0;
         conv(c, 1, XH, YW, XU, -1.0, G_ADMM);
         const int nl = std::max(1, cg_launch);
         for (int i = 0; i < nl; ++i)

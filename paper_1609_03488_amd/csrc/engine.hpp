@@ -240,6 +240,7 @@ class Engine {
     // products, the update takes the CG start test)
     void cg_iter(int z, int gate, int cg_max, int track, int it, int last = 0, int start = 0);
     // CG steps run folded into the A^T launch (FFT engine chosen and the tables allow it)
+    int idrows = 0;   // the right-hand side launch writes A p's identity rows (build)
     bool folded_cg() const { return fold_cg && prec == 1 && st.conv_mfma == 2 && !ca.empty() && ca[0].fft; }
     // relative floor of the ADMM steps' CG tolerance: cg_floor, and in FP64 at
     // most eps / 100 (subspace solves well below the target tolerance; FP32

@@ -40,6 +40,10 @@ struct ConvLaunch {
     // in the same launch, on kinds (out2, in2, base2) with the same sigma
     int pair;
     int out2, in2, base2;
+    // fold = 1: idrows = k + 1 also writes, for each identity block of A, the
+    // rows of Y kind k that A p has there for p = r: (T)(scale * r), the value
+    // the A launch's initialisation workgroups would write (0: none)
+    int idrows;
 };
 // dynamic LDS bytes of the convolution kernel for a staging pass of kc taps
 size_t conv_smem_bytes(int prec, int kc);
