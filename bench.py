@@ -110,7 +110,7 @@ def run_deconv(args, cfg):
     s = P.Solver(pr.op, pr.l, pr.q, st, stream=stream)
     s.set_data(0, pr.b, pr.c)
     log(f"workspace {s.workspace_bytes / 2**20:.1f} MiB")
-    engine = 1 if prec == P.FP32 else 0
+    engine = int(st.conv_mfma) if prec == P.FP32 else 0   # (the settings' default engine)
     if prec == P.FP32 and args.conv_engine is not None:
         engine = args.conv_engine
         s.close()

@@ -140,12 +140,12 @@ typedef struct {
                               dense blocks hold more than 65536 entries always take
                               the launch-per-kernel path (a dense product on one
                               workgroup is 20-80x slower than spread over the chip) */
-    int32_t conv_mfma;     /* FP32 convolution engine.  1 (default): matrix cores
+    int32_t conv_mfma;     /* FP32 convolution engine.  2 (default): FFT overlap-save
+                              (2048-point transforms in LDS, two real windows per
+                              complex transform) for kernels of up to 1536 taps,
+                              the matrix cores for longer ones; 1: matrix cores
                               (16x16x4 FP32 MFMA over Toeplitz blocks of the taps);
-                              2: FFT overlap-save (2048-point transforms in LDS, two
-                              real windows per complex transform) for kernels of up
-                              to 1536 taps, the matrix cores for longer ones; 0:
-                              vector ALU.  The products agree to their rounding
+                              0: vector ALU.  The products agree to their rounding
                               (elementwise for 0 and 1; normwise per 2048-point
                               window for 2)                                         */
     int32_t normalize;     /* data scaling the iteration runs on: 1 (default):

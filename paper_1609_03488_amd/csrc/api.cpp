@@ -295,7 +295,7 @@ void cgs_settings_default(cgs_settings* st) {
     st->cg_adaptive = 1;
     st->fused_max = 16384;
     st->fused_lone_max = 8192;
-    st->conv_mfma = 1;
+    st->conv_mfma = 2;
     st->normalize = 1;
     st->intervals_per_sync = 2;
 }
