@@ -581,37 +581,29 @@ DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, in
     for (int64_t t0 = 0; t0 < cb.kpad; t0 += KC) {
         const int kc = (int)((cb.kpad - t0) < KC ? (cb.kpad - t0) : KC);
         __syncthreads();
-        // stage the input window with 8 independent loads in flight per lane
+        // stage the input window and the taps, 8 entries of each per lane
+        // with all their loads in flight together (nwin > kc)
         const int64_t w0 = ot + off + t0;
         const int nwin = TILE + kc + 2 * R;
         for (int base = 0; base < nwin; base += 8 * NT) {
-            T v[8];
+            T v[8], tv[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int i = base + j * NT + tid;
                 const int64_t g = w0 + i;
                 v[j] = (i < nwin && g >= 0 && g < n_in) ? src[g] : T(0);
+                tv[j] = i < kc ? w[t0 + i] : T(0);
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int i = base + j * NT + tid;
                 if (i < nwin) win[i] = v[j];
-            }
-        }
-        for (int base = 0; base < kc; base += 8 * NT) {
-            T v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = base + j * NT + tid;
-                v[j] = i < kc ? w[t0 + i] : T(0);
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = base + j * NT + tid;
-                if (i < kc) taps[i] = v[j];
+                if (i < kc) taps[i] = tv[j];
             }
         }
         __syncthreads();
+        // a wave whose outputs all lie past the block's end skips the sums
+        if (ot + (int64_t)(tid & ~63) * R >= n_out) continue;
         const T* wp = win + tid * R;
         T a[R], b[R], tw[R];
         lds_vec<T, R>(a, wp);
@@ -640,10 +632,16 @@ DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, in
                                         s * (double)acc[r]);
         }
     } else {
+        T ov[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t oi = ot + (int64_t)tid * R + r;
-            if (oi < n_out) o[oi] = (T)((double)o[oi] + s * (double)acc[r]);
+            ov[r] = oi < n_out ? o[oi] : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t oi = ot + (int64_t)tid * R + r;
+            if (oi < n_out) o[oi] = (T)((double)ov[r] + s * (double)acc[r]);
         }
     }
     __syncthreads();

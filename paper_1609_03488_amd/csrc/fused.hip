@@ -19,6 +19,7 @@
 namespace cgs {
 
 constexpr int FNT = 512;   // threads per instance workgroup
+constexpr int FU = 4;      // elements per thread whose loads are issued together
 
 // Workgroup sum in a fixed order; every thread receives the result.
 DEVI double bsum(double v, double* sh) {
@@ -30,6 +31,29 @@ DEVI double bsum(double v, double* sh) {
 #pragma unroll
     for (int i = 0; i < FNT / 64; ++i) r += sh[i];
     return r;
+}
+
+// Elementwise pass over [0, len): the thread's elements tid + FNT j, FU at a
+// time, with all FU elements' loads (ld) issued before any of their stores
+// (st).  Element by element, every load would wait for the previous
+// element's stores (the compiler cannot tell the vectors apart), one L2 round
+// trip each.  Elements are visited in increasing j, so sums that st
+// accumulates keep the order of a plain loop.
+template <typename R, typename L, typename S>
+DEVI void ew(int64_t len, L ld, S st) {
+    for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)FNT * FU) {
+        R rg[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int64_t i = i0 + (int64_t)u * FNT;
+            if (i < len) ld(rg[u], i);
+        }
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int64_t i = i0 + (int64_t)u * FNT;
+            if (i < len) st(rg[u], i);
+        }
+    }
 }
 
 // out_rows += sigma * scale * W in (W = A or its stored transpose); a wave per row.
@@ -50,6 +74,60 @@ DEVI void dense_rows(const InstDesc& d, const DenseBlock& db, int adj, int out, 
     }
 }
 
+// out = base (or 0) + the identity blocks' terms, every entry of out: FU
+// elements at a time, their base and the inputs of up to four identity blocks
+// loaded together, then added block by block in the blocks' order.
+template <typename T>
+DEVI void f_identity(const Tables& tb, const InstDesc& d, int adj, gptr<T> o, gptr<const T> src,
+                     gptr<const T> bs, int64_t len, double sigma) {
+    constexpr int NB = 4;
+    for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)FNT * FU) {
+        double v[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int64_t i = i0 + (int64_t)u * FNT;
+            v[u] = (bs && i < len) ? (double)bs[i] : 0.0;
+        }
+        for (int b0 = d.id0; b0 < d.id1; b0 += NB) {
+            int64_t r0[NB], c0[NB], ln[NB];
+            double sb[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (b0 + b < d.id1) {
+                    const IdBlock ib = tb.ids[b0 + b];
+                    r0[b] = adj ? ib.col0 : ib.row0;
+                    c0[b] = adj ? ib.row0 : ib.col0;
+                    ln[b] = ib.len;
+                    sb[b] = ib.scale;
+                } else {
+                    r0[b] = c0[b] = ln[b] = 0;
+                    sb[b] = 0.0;
+                }
+            }
+            T x[NB][FU];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int u = 0; u < FU; ++u) {
+                    const int64_t i = i0 + (int64_t)u * FNT;
+                    x[b][u] = (i < len && i >= r0[b] && i < r0[b] + ln[b]) ? src[i - r0[b] + c0[b]] : T(0);
+                }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int u = 0; u < FU; ++u) {
+                    const int64_t i = i0 + (int64_t)u * FNT;
+                    if (i >= r0[b] && i < r0[b] + ln[b]) v[u] += sigma * sb[b] * (double)x[b][u];
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int64_t i = i0 + (int64_t)u * FNT;
+            if (i < len) o[i] = (T)v[u];
+        }
+    }
+}
+
 // out = base (or 0) + sigma * (A in) (adj = 0) or sigma * (A^T in) (adj = 1).
 template <typename T>
 DEVI void f_apply(const Tables& tb, const InstDesc& d, int adj, int out, int in, int base,
@@ -57,17 +135,7 @@ DEVI void f_apply(const Tables& tb, const InstDesc& d, int adj, int out, int in,
     gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
     gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
     gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
-    const int64_t len = adj ? d.n : d.m;
-    for (int64_t i = threadIdx.x; i < len; i += FNT) {
-        double v = bs ? (double)bs[i] : 0.0;
-        for (int b = d.id0; b < d.id1; ++b) {
-            const IdBlock ib = tb.ids[b];
-            const int64_t r0 = adj ? ib.col0 : ib.row0;
-            const int64_t c0 = adj ? ib.row0 : ib.col0;
-            if (i >= r0 && i < r0 + ib.len) v += sigma * ib.scale * (double)src[i - r0 + c0];
-        }
-        o[i] = (T)v;
-    }
+    f_identity<T>(tb, d, adj, o, src, bs, adj ? d.n : d.m, sigma);
     __syncthreads();
     constexpr int R = ConvCfg<T>::R;
     for (int c = d.cb0; c < d.cb1; ++c) {
@@ -86,7 +154,7 @@ DEVI void f_apply(const Tables& tb, const InstDesc& d, int adj, int out, int in,
 template <typename T>
 __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     extern __shared__ __align__(16) unsigned char fsmem[];
-    __shared__ double sh[FNT / 64];
+    __shared__ double sh[6 * (FNT / 64)];
     const InstDesc d = tb.inst[blockIdx.x];
     gptr<double> sc = scal(d);
     if (!(sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 2.0)) return;
@@ -107,26 +175,30 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     gptr<const T> gx = xvec<T>(d, XG), cx = xvec<T>(d, XC);
     gptr<T> uy = yvec<T>(d, YU), vs = yvec<T>(d, YV), wy = yvec<T>(d, YW), zy = yvec<T>(d, YZ);
     gptr<T> ty = yvec<T>(d, YT), az = yvec<T>(d, YA);
-    gptr<const T> by = yvec<T>(d, YB);
+    gptr<const T> by = yvec<T>(d, YB), gy = yvec<T>(d, YG);
     const double al = fa.alpha;
 
     for (int step = 0; step < fa.nsteps; ++step) {
         // w_y = u_y + v_s; h = u_x - A^T w_y
-        for (int64_t i = tid; i < m; i += FNT) wy[i] = (T)((double)uy[i] + (double)vs[i]);
+        struct V2 { T a, b; };
+        ew<V2>(m, [&](V2& r, int64_t i) { r.a = uy[i]; r.b = vs[i]; },
+               [&](V2& r, int64_t i) { wy[i] = (T)((double)r.a + (double)r.b); });
         __syncthreads();
         f_apply<T>(tb, d, 1, XH, YW, XU, -1.0, fa.kc, fsmem);
         // CG on (I + A^T A) z = h from the warm start (carried K z, A z)
-        double rr = 0.0, hh = 0.0;
-        for (int64_t i = tid; i < n; i += FNT) {
-            const double hi = (double)hx[i];
-            const T ri = (T)(hi - (double)kz[i]);
-            rx[i] = ri;
-            px[i] = ri;
-            rr = fma((double)ri, (double)ri, rr);
-            hh = fma(hi, hi, hh);
-        }
-        rr = bsum(rr, sh);
-        hh = bsum(hh, sh);
+        double s2[2] = {0.0, 0.0};   // ||r||^2, ||h||^2
+        ew<V2>(n, [&](V2& r, int64_t i) { r.a = hx[i]; r.b = kz[i]; },
+               [&](V2& r, int64_t i) {
+                   const double hi = (double)r.a;
+                   const T ri = (T)(hi - (double)r.b);
+                   rx[i] = ri;
+                   px[i] = ri;
+                   s2[0] = fma((double)ri, (double)ri, s2[0]);
+                   s2[1] = fma(hi, hi, s2[1]);
+               });
+        block_sumN<FNT, 2>(s2, sh);
+        double rr = s2[0];
+        const double hh = s2[1];
         double rel = fa.zeta > 0.0 ? fa.zeta / pow(iter + 1.0, fa.rate) : 0.0;
         rel = rel > fa.floor_ ? rel : fa.floor_;
         const double tol = sqrt(hh) * rel;
@@ -136,20 +208,24 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
             f_apply<T>(tb, d, 0, YT, XP, -1, 1.0, fa.kc, fsmem);       // A p
             f_apply<T>(tb, d, 1, XQ, YT, XP, 1.0, fa.kc, fsmem);       // q = p + A^T A p
             double pq = 0.0;
-            for (int64_t i = tid; i < n; i += FNT) pq = fma((double)px[i], (double)qx[i], pq);
+            ew<V2>(n, [&](V2& r, int64_t i) { r.a = px[i]; r.b = qx[i]; },
+                   [&](V2& r, int64_t i) { pq = fma((double)r.a, (double)r.b, pq); });
             pq = bsum(pq, sh);
             const double a = rr / pq;
             if (!(pq > 0.0 && std::isfinite(a))) break;
             double rn = 0.0;
-            for (int64_t i = tid; i < n; i += FNT) {
-                const double qi = (double)qx[i];
-                zx[i] = (T)fma(a, (double)px[i], (double)zx[i]);
-                const T ri = (T)fma(-a, qi, (double)rx[i]);
-                rx[i] = ri;
-                kz[i] = (T)fma(a, qi, (double)kz[i]);
-                rn = fma((double)ri, (double)ri, rn);
-            }
-            for (int64_t i = tid; i < m; i += FNT) az[i] = (T)fma(a, (double)ty[i], (double)az[i]);
+            struct V5 { T q, p, z, r, k; };
+            ew<V5>(n, [&](V5& r, int64_t i) { r.q = qx[i]; r.p = px[i]; r.z = zx[i]; r.r = rx[i]; r.k = kz[i]; },
+                   [&](V5& r, int64_t i) {
+                       const double qi = (double)r.q;
+                       zx[i] = (T)fma(a, (double)r.p, (double)r.z);
+                       const T ri = (T)fma(-a, qi, (double)r.r);
+                       rx[i] = ri;
+                       kz[i] = (T)fma(a, qi, (double)r.k);
+                       rn = fma((double)ri, (double)ri, rn);
+                   });
+            ew<V2>(m, [&](V2& r, int64_t i) { r.a = ty[i]; r.b = az[i]; },
+                   [&](V2& r, int64_t i) { az[i] = (T)fma(a, (double)r.a, (double)r.b); });
             rn = bsum(rn, sh);
             const double be = rr > 0.0 ? rn / rr : 0.0;
             rr = rn;
@@ -157,35 +233,47 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
             cgtot += 1.0;
             act = std::isfinite(rr) && sqrt(rr) > tol && cgit < fa.cg_max;
             if (act)
-                for (int64_t i = tid; i < n; i += FNT) px[i] = (T)fma(be, (double)px[i], (double)rx[i]);
+                ew<V2>(n, [&](V2& r, int64_t i) { r.a = px[i]; r.b = rx[i]; },
+                       [&](V2& r, int64_t i) { px[i] = (T)fma(be, (double)r.a, (double)r.b); });
             __syncthreads();
         }
         if (cgit > cgmax) cgmax = cgit;
         // z_y = w_y + A z; u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta
-        double cz = 0.0, bz = 0.0;
-        for (int64_t i = tid; i < n; i += FNT) cz = fma((double)cx[i], (double)zx[i], cz);
-        for (int64_t i = tid; i < m; i += FNT) {
-            const T zv = (T)((double)wy[i] + (double)az[i]);
-            zy[i] = zv;
-            bz = fma((double)by[i], (double)zv, bz);
-        }
-        cz = bsum(cz, sh);
-        bz = bsum(bz, sh);
+        double s3[2] = {0.0, 0.0};   // c^T z_x, b^T z_y
+        ew<V2>(n, [&](V2& r, int64_t i) { r.a = cx[i]; r.b = zx[i]; },
+               [&](V2& r, int64_t i) { s3[0] = fma((double)r.a, (double)r.b, s3[0]); });
+        struct V3 { T w, a, b; };
+        ew<V3>(m, [&](V3& r, int64_t i) { r.w = wy[i]; r.a = az[i]; r.b = by[i]; },
+               [&](V3& r, int64_t i) {
+                   const T zv = (T)((double)r.w + (double)r.a);
+                   zy[i] = zv;
+                   s3[1] = fma((double)r.b, (double)zv, s3[1]);
+               });
+        block_sumN<FNT, 2>(s3, sh);
+        const double cz = s3[0], bz = s3[1];
         ut = (tau + kap + cz + bz) / eta;
         const double ubar = al * ut + (1.0 - al) * tau;
         const double tnew = ubar - kap > 0.0 ? ubar - kap : 0.0;
         kap = kap - ubar + tnew;
         tau = tnew;
         iter += 1.0;
+        // relaxed point minus v_s of Y entry i, from its u_y, z_y, g_y, v_s
+        struct V4 { T u, z, g, v; };
+        auto ld4y = [&](V4& r, int64_t i) { r.u = uy[i]; r.z = zy[i]; r.g = gy[i]; r.v = vs[i]; };
+        auto pv_of = [&](const V4& r) {
+            const double ut_y = (double)r.z - ut * (double)r.g;
+            const double ub = al * ut_y + (1.0 - al) * (double)r.u;
+            return ub - (double)r.v;
+        };
         // second-order cones: head and tail norm of u_bar_y - v_s
         for (int sgi = d.sg0; sgi < d.sg1; ++sgi) {
             const SocSeg sg = tb.seg[sgi];
             double ss = 0.0;
-            for (int64_t i = sg.start + 1 + tid; i < sg.start + sg.len; i += FNT) {
-                double ub;
-                const double pv = ybar_minus_v<T>(d, i, ut, al, ub);
-                ss = fma(pv, pv, ss);
-            }
+            ew<V4>(sg.len - 1, [&](V4& r, int64_t i) { ld4y(r, sg.start + 1 + i); },
+                   [&](V4& r, int64_t) {
+                       const double pv = pv_of(r);
+                       ss = fma(pv, pv, ss);
+                   });
             ss = bsum(ss, sh);
             if (tid == 0) {
                 double ub;
@@ -195,15 +283,17 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         }
         __syncthreads();
         // relaxation, projection, dual update
-        for (int64_t i = tid; i < n; i += FNT)
-            ux[i] = (T)(al * ((double)zx[i] - ut * (double)gx[i]) + (1.0 - al) * (double)ux[i]);
-        for (int64_t i = tid; i < d.l; i += FNT) {
-            double ub;
-            const double pv = ybar_minus_v<T>(d, i, ut, al, ub);
+        struct V3x { T z, g, u; };
+        ew<V3x>(n, [&](V3x& r, int64_t i) { r.z = zx[i]; r.g = gx[i]; r.u = ux[i]; },
+                [&](V3x& r, int64_t i) {
+                    ux[i] = (T)(al * ((double)r.z - ut * (double)r.g) + (1.0 - al) * (double)r.u);
+                });
+        ew<V4>(d.l, ld4y, [&](V4& r, int64_t i) {
+            const double pv = pv_of(r);
             const double pr = pv > 0.0 ? pv : 0.0;
             uy[i] = (T)pr;
             vs[i] = (T)(pr - pv);
-        }
+        });
         for (int sgi = d.sg0; sgi < d.sg1; ++sgi) {
             const SocSeg sg = tb.seg[sgi];
             const double t = tb.seg_val[2 * sgi];
@@ -216,16 +306,16 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
                 mode = 2;
                 aa = 0.5 * (t + nz);
             }
-            for (int64_t i = sg.start + tid; i < sg.start + sg.len; i += FNT) {
-                double ub;
-                const double pv = ybar_minus_v<T>(d, i, ut, al, ub);
-                double pr;
-                if (mode == 0) pr = pv;
-                else if (mode == 1) pr = 0.0;
-                else pr = (i == sg.start) ? aa : (aa / nz) * pv;
-                uy[i] = (T)pr;
-                vs[i] = (T)(pr - pv);
-            }
+            ew<V4>(sg.len, [&](V4& r, int64_t i) { ld4y(r, sg.start + i); },
+                   [&](V4& r, int64_t i) {
+                       const double pv = pv_of(r);
+                       double pr;
+                       if (mode == 0) pr = pv;
+                       else if (mode == 1) pr = 0.0;
+                       else pr = (i == 0) ? aa : (aa / nz) * pv;
+                       uy[sg.start + i] = (T)pr;
+                       vs[sg.start + i] = (T)(pr - pv);
+                   });
         }
         __syncthreads();
     }
@@ -234,28 +324,32 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     if (fa.check) {
         f_apply<T>(tb, d, 0, YT, XU, -1, 1.0, fa.kc, fsmem);   // A u_x
         f_apply<T>(tb, d, 1, XT, YU, -1, 1.0, fa.kc, fsmem);   // A^T u_y
-        double y0 = 0, y1 = 0, y2 = 0, x0 = 0, x1 = 0, x2 = 0;
         gptr<const T> aty = xvec<T>(d, XT);
         gptr<const T> dr = yvec<T>(d, YD);
         gptr<const T> ec = xvec<T>(d, XE);
-        for (int64_t i = tid; i < m; i += FNT) {
-            const double w = 1.0 / (double)dr[i];
-            const double e = ((double)ty[i] + (double)vs[i]) * w;
-            const double rp = e - tau * (double)by[i] * w;
-            y0 = fma(rp, rp, y0);
-            y1 = fma(e, e, y1);
-            y2 = fma((double)by[i], (double)uy[i], y2);
-        }
-        for (int64_t i = tid; i < n; i += FNT) {
-            const double w = 1.0 / (double)ec[i];
-            const double e = (double)aty[i] * w;
-            const double rd = e + tau * (double)cx[i] * w;
-            x0 = fma(rd, rd, x0);
-            x1 = fma(e, e, x1);
-            x2 = fma((double)cx[i], (double)ux[i], x2);
-        }
-        y0 = bsum(y0, sh); y1 = bsum(y1, sh); y2 = bsum(y2, sh);
-        x0 = bsum(x0, sh); x1 = bsum(x1, sh); x2 = bsum(x2, sh);
+        double r6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // Y: 0-2, X: 3-5
+        struct V5y { T d, t, v, b, u; };
+        ew<V5y>(m, [&](V5y& r, int64_t i) { r.d = dr[i]; r.t = ty[i]; r.v = vs[i]; r.b = by[i]; r.u = uy[i]; },
+                [&](V5y& r, int64_t) {
+                    const double w = 1.0 / (double)r.d;
+                    const double e = ((double)r.t + (double)r.v) * w;
+                    const double rp = e - tau * (double)r.b * w;
+                    r6[0] = fma(rp, rp, r6[0]);
+                    r6[1] = fma(e, e, r6[1]);
+                    r6[2] = fma((double)r.b, (double)r.u, r6[2]);
+                });
+        struct V4x { T e, a, c, u; };
+        ew<V4x>(n, [&](V4x& r, int64_t i) { r.e = ec[i]; r.a = aty[i]; r.c = cx[i]; r.u = ux[i]; },
+                [&](V4x& r, int64_t) {
+                    const double w = 1.0 / (double)r.e;
+                    const double e = (double)r.a * w;
+                    const double rd = e + tau * (double)r.c * w;
+                    r6[3] = fma(rd, rd, r6[3]);
+                    r6[4] = fma(e, e, r6[4]);
+                    r6[5] = fma((double)r.c, (double)r.u, r6[5]);
+                });
+        block_sumN<FNT, 6>(r6, sh);
+        const double y0 = r6[0], y1 = r6[1], y2 = r6[2], x0 = r6[3], x1 = r6[4], x2 = r6[5];
         const CheckOut co = check_outcome(sc, tau, kap, iter, y0, y1, y2, x0, x1, x2, fa.eps,
                                           fa.max_iters);
         status = co.status;
