@@ -543,38 +543,22 @@ DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, 
     return ubar - (double)yvec<T>(d, YV)[i];
 }
 
-// One tile of NT * R consecutive outputs (from `ot`) of a convolution block
-// (adj = 0: A, out is Y; adj = 1: A^T, out is X), out += sigma * scale * (...).
-// smem: (NT * R + 2 * KC + 2R) elements of T.  Called by every thread of the
-// workgroup; starts and ends with a workgroup barrier.
-template <typename T, int NT>
-DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, int in, double sigma,
-                    int64_t ot, int KC, unsigned char* smem, const IdBlock* ids = nullptr,
-                    int base = -1) {
+// The sums of one tile of NT * R consecutive outputs (from `ot`) of a
+// convolution block (adj = 0: A, adj = 1: A^T): acc[r] = the unscaled sum for
+// output ot + R threadIdx.x + r.  src points at the block's first input (any
+// address space).  smem: (NT * R + 2 * KC + 2R) elements of T.  Called by every
+// thread of the workgroup; each chunk of taps starts with a workgroup barrier.
+template <typename T, int NT, typename PC>
+DEVI void conv_sums(const ConvBlock& cb, int adj, PC src, int64_t ot, int KC, unsigned char* smem,
+                    T (&acc)[ConvCfg<T>::R]) {
     constexpr int R = ConvCfg<T>::R, TILE = NT * R;
     T* win = reinterpret_cast<T*>(smem);        // TILE + KC + 2R entries
     T* taps = win + TILE + KC + 2 * R;          // KC entries
-    int64_t n_out, n_in, off;
-    gptr<const T> w;
-    gptr<T> o;
-    gptr<const T> src;
-    if (!adj) {
-        n_out = cb.n_in + cb.k - 1;
-        n_in = cb.n_in;
-        off = -(cb.k - 1);
-        w = (gptr<const T>)cb.w_fwd;
-        o = yvec<T>(d, out) + cb.row0;
-        src = xvec<T>(d, in) + cb.col0;
-    } else {
-        n_out = cb.n_in;
-        n_in = cb.n_in + cb.k - 1;
-        off = 0;
-        w = (gptr<const T>)cb.w_adj;
-        o = xvec<T>(d, out) + cb.col0;
-        src = yvec<T>(d, in) + cb.row0;
-    }
+    const int64_t n_out = adj ? cb.n_in : cb.n_in + cb.k - 1;
+    const int64_t n_in = adj ? cb.n_in + cb.k - 1 : cb.n_in;
+    const int64_t off = adj ? 0 : -(cb.k - 1);
+    gptr<const T> w = (gptr<const T>)(adj ? cb.w_adj : cb.w_fwd);
     const int tid = threadIdx.x;
-    T acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = T(0);
 
@@ -622,6 +606,25 @@ DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, in
             conv_step<T, R>(acc, a, b, tw);
         }
     }
+}
+
+// One tile of NT * R consecutive outputs (from `ot`) of a convolution block
+// (adj = 0: A, out is Y; adj = 1: A^T, out is X), out += sigma * scale * (...),
+// or, when ids is given and the block owns its output range, out = the
+// element's base and identity-block terms + sigma * scale * (...).
+// smem: (NT * R + 2 * KC + 2R) elements of T.  Called by every thread of the
+// workgroup; starts and ends with a workgroup barrier.
+template <typename T, int NT>
+DEVI void conv_tile(const InstDesc& d, const ConvBlock& cb, int adj, int out, int in, double sigma,
+                    int64_t ot, int KC, unsigned char* smem, const IdBlock* ids = nullptr,
+                    int base = -1) {
+    constexpr int R = ConvCfg<T>::R;
+    const int64_t n_out = adj ? cb.n_in : cb.n_in + cb.k - 1;
+    gptr<T> o = adj ? xvec<T>(d, out) + cb.col0 : yvec<T>(d, out) + cb.row0;
+    gptr<const T> src = adj ? yvec<T>(d, in) + cb.row0 : xvec<T>(d, in) + cb.col0;
+    const int tid = threadIdx.x;
+    T acc[R];
+    conv_sums<T, NT>(cb, adj, src, ot, KC, smem, acc);
     const double s = sigma * cb.scale;
     if (ids && (cb.own >> adj) & 1) {
 #pragma unroll

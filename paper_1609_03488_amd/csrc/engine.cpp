@@ -579,6 +579,10 @@ int Engine::build(const std::vector<InstRec>& r) {
         d.fused = (st.fused_max > 0 && !use_gemm && d.n + d.m <= lim && dense <= FUSED_DENSE_MAX) ? 1 : 0;
         (d.fused ? n_fused : n_multi) += 1;
     }
+    fused_res = 0;
+    for (const InstDesc& d : im.inst)
+        if (d.fused) fused_res = std::max(fused_res, fused_resident_bytes(prec, d.n, d.m));
+    if (n_fused) fused_prepare();
     // When every convolution owns its output range in a direction, the output
     // initialisation rides on the first convolution launch as extra
     // workgroups (one launch fewer per apply); tiles wholly inside an owned
@@ -944,6 +948,7 @@ void Engine::fused_steps(int nsteps, int check) {
     fa.cg_max = st.cg_max_iters;
     fa.max_iters = st.max_iters;
     fa.kc = fused_kc;
+    fa.res_want = fused_res;
     launch_fused(prec, T, fa, stream);
 }
 

@@ -199,6 +199,7 @@ class Engine {
     int n_fused = 0, n_multi = 0;
     int lone = 0;                // a solver with a single instance (fused_lone_max applies)
     int fused_kc = 8;
+    int64_t fused_res = 0;        // LDS bytes of the largest fused instance's resident vectors
     // batched BF16 MFMA path for dense blocks shared by every instance
     int use_gemm = 0;
     int gemm_corr = 0;           // 1: add the refinement products (hi x lo)

@@ -10,6 +10,7 @@
 // the same as in the multi-kernel path; only the reduction trees differ.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -56,14 +57,66 @@ DEVI void ew(int64_t len, L ld, S st) {
     }
 }
 
+// Where an instance's vectors live during a fused launch.  Every vector
+// starts in the instance's region of global memory; the ones the CG loop and
+// the step's other passes touch most are moved into the workgroup's LDS for the
+// launch when they fit (a flat pointer reaches either), in the order of
+// kResident, and written back at its end.  Only where the values sit changes:
+// the arithmetic is the same.
+template <typename T>
+struct FVecs {
+    T* x[NXV];
+    T* y[NYV];
+    unsigned res;   // bit j: kResident[j] is in LDS
+};
+// (X vectors below NXV, Y vectors as NXV + their index)
+constexpr int kResident[] = {XP, XQ, XR, XZ, XK, NXV + YT, NXV + YA, XH, NXV + YW, NXV + YZ};
+constexpr int kNumResident = sizeof(kResident) / sizeof(kResident[0]);
+// carried from one launch to the next (the others are written before they are read)
+constexpr bool resident_live(int v) { return v == XZ || v == XK || v == NXV + YA; }
+
+template <typename T>
+DEVI T*& fv_slot(FVecs<T>& fv, int v) { return v < NXV ? fv.x[v] : fv.y[v - NXV]; }
+
+// Copy every resident vector between LDS and the instance's region: to LDS
+// (in = true: only the vectors that hold live values) or back (in = false).
+template <typename T>
+DEVI void fv_copy(const InstDesc& d, FVecs<T>& fv, bool in) {
+#pragma unroll
+    for (int j = 0; j < kNumResident; ++j) {
+        if (!((fv.res >> j) & 1u)) continue;
+        const int v = kResident[j];
+        if (in && !resident_live(v)) continue;
+        T* lds = fv_slot(fv, v);
+        T* glb = v < NXV ? (T*)xvec<T>(d, v) : (T*)yvec<T>(d, v - NXV);
+        const int64_t len = v < NXV ? d.n : d.m;
+        T* dst = in ? lds : glb;
+        const T* src = in ? glb : lds;
+        for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)FNT * 8) {
+            T t[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + (int64_t)u * FNT;
+                if (i < len) t[u] = src[i];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = i0 + (int64_t)u * FNT;
+                if (i < len) dst[i] = t[u];
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // out_rows += sigma * scale * W in (W = A or its stored transpose); a wave per row.
 template <typename T>
-DEVI void dense_rows(const InstDesc& d, const DenseBlock& db, int adj, int out, int in, double sigma) {
+DEVI void dense_rows(const DenseBlock& db, int adj, T* out, const T* in, double sigma) {
     gptr<const T> a = (gptr<const T>)(adj ? db.at : db.a);
     const int64_t ld = adj ? db.ldt : db.ld;
     const int64_t nrows = adj ? db.cols : db.rows, ncols = adj ? db.rows : db.cols;
-    gptr<T> o = adj ? xvec<T>(d, out) + db.col0 : yvec<T>(d, out) + db.row0;
-    gptr<const T> x = adj ? yvec<T>(d, in) + db.row0 : xvec<T>(d, in) + db.col0;
+    T* o = out + (adj ? db.col0 : db.row0);
+    const T* x = in + (adj ? db.row0 : db.col0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const double s = sigma * db.scale;
     for (int64_t r = wave; r < nrows; r += FNT / 64) {
@@ -78,8 +131,8 @@ DEVI void dense_rows(const InstDesc& d, const DenseBlock& db, int adj, int out, 
 // elements at a time, their base and the inputs of up to four identity blocks
 // loaded together, then added block by block in the blocks' order.
 template <typename T>
-DEVI void f_identity(const Tables& tb, const InstDesc& d, int adj, gptr<T> o, gptr<const T> src,
-                     gptr<const T> bs, int64_t len, double sigma) {
+DEVI void f_identity(const Tables& tb, const InstDesc& d, int adj, T* o, const T* src, const T* bs,
+                     int64_t len, double sigma) {
     constexpr int NB = 4;
     for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)FNT * FU) {
         double v[FU];
@@ -130,23 +183,36 @@ DEVI void f_identity(const Tables& tb, const InstDesc& d, int adj, gptr<T> o, gp
 
 // out = base (or 0) + sigma * (A in) (adj = 0) or sigma * (A^T in) (adj = 1).
 template <typename T>
-DEVI void f_apply(const Tables& tb, const InstDesc& d, int adj, int out, int in, int base,
+DEVI void f_apply(const Tables& tb, const InstDesc& d, int adj, T* o, const T* src, const T* bs,
                   double sigma, int kc, unsigned char* smem) {
-    gptr<T> o = adj ? xvec<T>(d, out) : yvec<T>(d, out);
-    gptr<const T> src = adj ? yvec<T>(d, in) : xvec<T>(d, in);
-    gptr<const T> bs = base >= 0 ? (adj ? xvec<T>(d, base) : yvec<T>(d, base)) : nullptr;
     f_identity<T>(tb, d, adj, o, src, bs, adj ? d.n : d.m, sigma);
-    __syncthreads();
     constexpr int R = ConvCfg<T>::R;
+    const int tid = threadIdx.x;
     for (int c = d.cb0; c < d.cb1; ++c) {
         const ConvBlock cb = tb.cblk[c];
         const int64_t n_out = adj ? cb.n_in : cb.n_in + cb.k - 1;
-        for (int64_t ot = 0; ot < n_out; ot += (int64_t)FNT * R)
-            conv_tile<T, FNT>(d, cb, adj, out, in, sigma, ot, kc, smem);
+        T* ob = o + (adj ? cb.col0 : cb.row0);
+        const T* ib = src + (adj ? cb.row0 : cb.col0);
+        const double s = sigma * cb.scale;
+        for (int64_t ot = 0; ot < n_out; ot += (int64_t)FNT * R) {
+            T acc[R];
+            conv_sums<T, FNT>(cb, adj, ib, ot, kc, smem, acc);   // (its first barrier orders o's writes)
+            T ov[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t oi = ot + (int64_t)tid * R + r;
+                ov[r] = oi < n_out ? ob[oi] : T(0);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t oi = ot + (int64_t)tid * R + r;
+                if (oi < n_out) ob[oi] = (T)((double)ov[r] + s * (double)acc[r]);
+            }
+        }
     }
+    __syncthreads();
     for (int q = d.db0; q < d.db1; ++q) {
-        const DenseBlock db = tb.dblk[q];
-        dense_rows<T>(d, db, adj, out, in, sigma);
+        dense_rows<T>(tb.dblk[q], adj, o, src, sigma);
         __syncthreads();
     }
 }
@@ -158,24 +224,48 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     const InstDesc d = tb.inst[blockIdx.x];
     gptr<double> sc = scal(d);
     if (!(sc[SC_ACTIVE] != 0.0 && sc[SC_PHASE] == 2.0)) return;
+    FVecs<T> fv;
+#pragma unroll
+    for (int k = 0; k < NXV; ++k) fv.x[k] = (T*)xvec<T>(d, k);
+#pragma unroll
+    for (int k = 0; k < NYV; ++k) fv.y[k] = (T*)yvec<T>(d, k);
+    fv.res = 0u;
     if (fa.refresh) {
         // the same applies as the exact recomputation at a check, so that a
         // refresh between checks leaves the carried products bitwise unchanged
-        f_apply<T>(tb, d, 0, YA, XZ, -1, 1.0, fa.kc, fsmem);
-        f_apply<T>(tb, d, 1, XK, YA, XZ, 1.0, fa.kc, fsmem);
+        f_apply<T>(tb, d, 0, fv.y[YA], fv.x[XZ], nullptr, 1.0, fa.kc, fsmem);
+        f_apply<T>(tb, d, 1, fv.x[XK], fv.y[YA], fv.x[XZ], 1.0, fa.kc, fsmem);
         return;
+    }
+    {
+        // LDS past the convolution's staging area, vector by vector in the
+        // order of kResident while they fit
+        unsigned char* p = fsmem + fa.lds_conv;
+        int64_t left = fa.lds_res;
+#pragma unroll
+        for (int j = 0; j < kNumResident; ++j) {
+            const int v = kResident[j];
+            const int64_t bytes = (((v < NXV ? d.n : d.m) * (int64_t)sizeof(T)) + 15) & ~int64_t(15);
+            if (bytes <= left) {
+                fv_slot(fv, v) = reinterpret_cast<T*>(p);
+                p += bytes;
+                left -= bytes;
+                fv.res |= 1u << j;
+            }
+        }
+        fv_copy<T>(d, fv, true);
     }
     const int tid = threadIdx.x;
     const int64_t n = d.n, m = d.m;
     double tau = sc[SC_TAU], kap = sc[SC_KAPPA], ut = sc[SC_UT];
     const double eta = sc[SC_ETA];
     double iter = sc[SC_ITER], cgtot = sc[SC_CGTOT], cgmax = sc[SC_CGMAX];
-    gptr<T> ux = xvec<T>(d, XU), zx = xvec<T>(d, XZ), rx = xvec<T>(d, XR), px = xvec<T>(d, XP);
-    gptr<T> qx = xvec<T>(d, XQ), hx = xvec<T>(d, XH), kz = xvec<T>(d, XK);
-    gptr<const T> gx = xvec<T>(d, XG), cx = xvec<T>(d, XC);
-    gptr<T> uy = yvec<T>(d, YU), vs = yvec<T>(d, YV), wy = yvec<T>(d, YW), zy = yvec<T>(d, YZ);
-    gptr<T> ty = yvec<T>(d, YT), az = yvec<T>(d, YA);
-    gptr<const T> by = yvec<T>(d, YB), gy = yvec<T>(d, YG);
+    T *ux = fv.x[XU], *zx = fv.x[XZ], *rx = fv.x[XR], *px = fv.x[XP];
+    T *qx = fv.x[XQ], *hx = fv.x[XH], *kz = fv.x[XK];
+    const T *gx = fv.x[XG], *cx = fv.x[XC];
+    T *uy = fv.y[YU], *vs = fv.y[YV], *wy = fv.y[YW], *zy = fv.y[YZ];
+    T *ty = fv.y[YT], *az = fv.y[YA];
+    const T *by = fv.y[YB], *gy = fv.y[YG];
     const double al = fa.alpha;
 
     for (int step = 0; step < fa.nsteps; ++step) {
@@ -184,7 +274,7 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         ew<V2>(m, [&](V2& r, int64_t i) { r.a = uy[i]; r.b = vs[i]; },
                [&](V2& r, int64_t i) { wy[i] = (T)((double)r.a + (double)r.b); });
         __syncthreads();
-        f_apply<T>(tb, d, 1, XH, YW, XU, -1.0, fa.kc, fsmem);
+        f_apply<T>(tb, d, 1, hx, wy, ux, -1.0, fa.kc, fsmem);
         // CG on (I + A^T A) z = h from the warm start (carried K z, A z)
         double s2[2] = {0.0, 0.0};   // ||r||^2, ||h||^2
         ew<V2>(n, [&](V2& r, int64_t i) { r.a = hx[i]; r.b = kz[i]; },
@@ -205,8 +295,8 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         int cgit = 0;
         bool act = fa.cg_max > 0 && std::isfinite(rr) && sqrt(rr) > tol;
         while (act) {
-            f_apply<T>(tb, d, 0, YT, XP, -1, 1.0, fa.kc, fsmem);       // A p
-            f_apply<T>(tb, d, 1, XQ, YT, XP, 1.0, fa.kc, fsmem);       // q = p + A^T A p
+            f_apply<T>(tb, d, 0, ty, px, nullptr, 1.0, fa.kc, fsmem);   // A p
+            f_apply<T>(tb, d, 1, qx, ty, px, 1.0, fa.kc, fsmem);        // q = p + A^T A p
             double pq = 0.0;
             ew<V2>(n, [&](V2& r, int64_t i) { r.a = px[i]; r.b = qx[i]; },
                    [&](V2& r, int64_t i) { pq = fma((double)r.a, (double)r.b, pq); });
@@ -276,8 +366,9 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
                    });
             ss = bsum(ss, sh);
             if (tid == 0) {
-                double ub;
-                tb.seg_val[2 * sgi] = ybar_minus_v<T>(d, sg.start, ut, al, ub);
+                V4 r;
+                ld4y(r, sg.start);
+                tb.seg_val[2 * sgi] = pv_of(r);
                 tb.seg_val[2 * sgi + 1] = ss;
             }
         }
@@ -322,11 +413,11 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
 
     double status = 0.0;
     if (fa.check) {
-        f_apply<T>(tb, d, 0, YT, XU, -1, 1.0, fa.kc, fsmem);   // A u_x
-        f_apply<T>(tb, d, 1, XT, YU, -1, 1.0, fa.kc, fsmem);   // A^T u_y
-        gptr<const T> aty = xvec<T>(d, XT);
-        gptr<const T> dr = yvec<T>(d, YD);
-        gptr<const T> ec = xvec<T>(d, XE);
+        f_apply<T>(tb, d, 0, ty, ux, nullptr, 1.0, fa.kc, fsmem);          // A u_x
+        f_apply<T>(tb, d, 1, fv.x[XT], uy, nullptr, 1.0, fa.kc, fsmem);    // A^T u_y
+        const T* aty = fv.x[XT];
+        const T* dr = fv.y[YD];
+        const T* ec = fv.x[XE];
         double r6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // Y: 0-2, X: 3-5
         struct V5y { T d, t, v, b, u; };
         ew<V5y>(m, [&](V5y& r, int64_t i) { r.d = dr[i]; r.t = ty[i]; r.v = vs[i]; r.b = by[i]; r.u = uy[i]; },
@@ -364,11 +455,12 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         }
         if (status == 0.0) {
             // exact recomputation of the carried products of the warm start
-            f_apply<T>(tb, d, 0, YA, XZ, -1, 1.0, fa.kc, fsmem);
-            f_apply<T>(tb, d, 1, XK, YA, XZ, 1.0, fa.kc, fsmem);
+            f_apply<T>(tb, d, 0, az, zx, nullptr, 1.0, fa.kc, fsmem);
+            f_apply<T>(tb, d, 1, kz, az, zx, 1.0, fa.kc, fsmem);
         }
     }
     __syncthreads();
+    fv_copy<T>(d, fv, false);
     if (tid == 0) {
         sc[SC_TAU] = tau;
         sc[SC_KAPPA] = kap;
@@ -393,9 +485,54 @@ size_t fused_smem_bytes(int prec, int kc) {
     return (size_t)(FNT * R + 2 * kc + 2 * R) * (prec == 0 ? 8 : 4);
 }
 
-void launch_fused(int prec, const Tables& t, const FusedArgs& fa, hipStream_t st) {
+int64_t fused_resident_bytes(int prec, int64_t n, int64_t m) {
+    const int64_t es = prec == 0 ? 8 : 4;
+    int64_t b = 0;
+    for (int j = 0; j < kNumResident; ++j)
+        b += (((kResident[j] < NXV ? n : m) * es) + 15) & ~int64_t(15);
+    return b;
+}
+
+// Dynamic LDS per workgroup that the fused kernels may take on each device
+// (0: not yet queried; then what fits in the 64 KB that needs no attribute)
+static int g_fused_lds[64] = {0};
+
+static int fused_static_lds() {
+    int b = 0;
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, (const void*)k_fused<double>) == hipSuccess) b = std::max(b, (int)a.sharedSizeBytes);
+    if (hipFuncGetAttributes(&a, (const void*)k_fused<float>) == hipSuccess) b = std::max(b, (int)a.sharedSizeBytes);
+    return b > 0 ? b : 1024;
+}
+
+int fused_prepare() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536 - 1024;
+    if (g_fused_lds[dev] == 0) {
+        const int fixed = fused_static_lds();   // the kernels' own __shared__ arrays
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        int dyn = v - fixed;
+        if (dyn > 65536 - fixed &&
+            (hipFuncSetAttribute((const void*)k_fused<double>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) !=
+                 hipSuccess ||
+             hipFuncSetAttribute((const void*)k_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) !=
+                 hipSuccess))
+            dyn = 65536 - fixed;
+        g_fused_lds[dev] = dyn;
+    }
+    return g_fused_lds[dev];
+}
+
+void launch_fused(int prec, const Tables& t, FusedArgs fa, hipStream_t st) {
     if (t.ninst <= 0) return;
-    const size_t lds = fused_smem_bytes(prec, fa.kc);
+    int dev = 0;
+    const int cap = (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && g_fused_lds[dev] > 0)
+                        ? g_fused_lds[dev] : 65536 - 1024;
+    fa.lds_conv = ((int64_t)fused_smem_bytes(prec, fa.kc) + 15) & ~int64_t(15);
+    fa.lds_res = std::max<int64_t>(0, std::min<int64_t>(fa.res_want, (int64_t)cap - fa.lds_conv));
+    const size_t lds = (size_t)(fa.lds_conv + fa.lds_res);
     if (prec == 0) k_fused<double><<<t.ninst, FNT, lds, st>>>(t, fa);
     else k_fused<float><<<t.ninst, FNT, lds, st>>>(t, fa);
 }

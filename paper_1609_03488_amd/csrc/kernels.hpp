@@ -181,9 +181,19 @@ struct FusedArgs {
     int cg_max;
     int max_iters;
     int kc;          // taps per LDS staging pass (as ConvLaunch::kc)
+    // set by launch_fused: LDS bytes of the convolution's staging area, and
+    // the bytes after it that hold an instance's most used vectors
+    int64_t lds_conv, lds_res;
+    int64_t res_want;   // bytes those vectors of the largest instance take (0: none)
 };
 size_t fused_smem_bytes(int prec, int kc);
-void launch_fused(int prec, const Tables& t, const FusedArgs& fa, hipStream_t st);
+// bytes that every resident-vector candidate of an instance with n variables
+// and m rows takes in LDS (16-byte aligned each)
+int64_t fused_resident_bytes(int prec, int64_t n, int64_t m);
+// queries the device's LDS per workgroup and lets the fused kernels take it
+// (once per device, outside any stream capture); returns that limit
+int fused_prepare();
+void launch_fused(int prec, const Tables& t, FusedArgs fa, hipStream_t st);
 
 // ---- batched dense applies as BF16 MFMA GEMMs (gemm.hip)
 struct GemmPlan {
