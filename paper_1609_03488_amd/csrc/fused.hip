@@ -20,7 +20,7 @@
 namespace cgs {
 
 constexpr int FNT = 512;   // threads per instance workgroup
-constexpr int FU = 4;      // elements per thread whose loads are issued together
+constexpr int FU = 2;      // elements per thread whose loads are issued together
 
 // Workgroup sum in a fixed order; every thread receives the result.
 DEVI double bsum(double v, double* sh) {
@@ -37,21 +37,23 @@ DEVI double bsum(double v, double* sh) {
 // Elementwise pass over [0, len): the thread's elements tid + FNT j, FU at a
 // time, with all FU elements' loads (ld) issued before any of their stores
 // (st).  Element by element, every load would wait for the previous
-// element's stores (the compiler cannot tell the vectors apart), one L2 round
-// trip each.  Elements are visited in increasing j, so sums that st
-// accumulates keep the order of a plain loop.
+// element's stores (the compiler cannot tell the vectors apart), one memory
+// round trip each; more than two at a time measured slower (code size).
+// Elements are visited in increasing j, so sums that st accumulates keep the
+// order of a plain loop.  Indices are 32-bit: an instance on this path has
+// n + m <= fused_max.
 template <typename R, typename L, typename S>
-DEVI void ew(int64_t len, L ld, S st) {
-    for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)FNT * FU) {
+DEVI void ew(int len, L ld, S st) {
+    for (int i0 = threadIdx.x; i0 < len; i0 += FNT * FU) {
         R rg[FU];
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
-            const int64_t i = i0 + (int64_t)u * FNT;
+            const int i = i0 + u * FNT;
             if (i < len) ld(rg[u], i);
         }
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
-            const int64_t i = i0 + (int64_t)u * FNT;
+            const int i = i0 + u * FNT;
             if (i < len) st(rg[u], i);
         }
     }
@@ -132,25 +134,26 @@ DEVI void dense_rows(const DenseBlock& db, int adj, T* out, const T* in, double 
 // loaded together, then added block by block in the blocks' order.
 template <typename T>
 DEVI void f_identity(const Tables& tb, const InstDesc& d, int adj, T* o, const T* src, const T* bs,
-                     int64_t len, double sigma) {
+                     int64_t len64, double sigma) {
     constexpr int NB = 4;
-    for (int64_t i0 = threadIdx.x; i0 < len; i0 += (int64_t)FNT * FU) {
+    const int len = (int)len64;
+    for (int i0 = threadIdx.x; i0 < len; i0 += FNT * FU) {
         double v[FU];
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
-            const int64_t i = i0 + (int64_t)u * FNT;
+            const int i = i0 + u * FNT;
             v[u] = (bs && i < len) ? (double)bs[i] : 0.0;
         }
         for (int b0 = d.id0; b0 < d.id1; b0 += NB) {
-            int64_t r0[NB], c0[NB], ln[NB];
+            int r0[NB], c0[NB], ln[NB];
             double sb[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 if (b0 + b < d.id1) {
                     const IdBlock ib = tb.ids[b0 + b];
-                    r0[b] = adj ? ib.col0 : ib.row0;
-                    c0[b] = adj ? ib.row0 : ib.col0;
-                    ln[b] = ib.len;
+                    r0[b] = (int)(adj ? ib.col0 : ib.row0);
+                    c0[b] = (int)(adj ? ib.row0 : ib.col0);
+                    ln[b] = (int)ib.len;
                     sb[b] = ib.scale;
                 } else {
                     r0[b] = c0[b] = ln[b] = 0;
@@ -162,20 +165,20 @@ DEVI void f_identity(const Tables& tb, const InstDesc& d, int adj, T* o, const T
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int u = 0; u < FU; ++u) {
-                    const int64_t i = i0 + (int64_t)u * FNT;
+                    const int i = i0 + u * FNT;
                     x[b][u] = (i < len && i >= r0[b] && i < r0[b] + ln[b]) ? src[i - r0[b] + c0[b]] : T(0);
                 }
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int u = 0; u < FU; ++u) {
-                    const int64_t i = i0 + (int64_t)u * FNT;
+                    const int i = i0 + u * FNT;
                     if (i >= r0[b] && i < r0[b] + ln[b]) v[u] += sigma * sb[b] * (double)x[b][u];
                 }
         }
 #pragma unroll
         for (int u = 0; u < FU; ++u) {
-            const int64_t i = i0 + (int64_t)u * FNT;
+            const int i = i0 + u * FNT;
             if (i < len) o[i] = (T)v[u];
         }
     }
@@ -271,14 +274,14 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
     for (int step = 0; step < fa.nsteps; ++step) {
         // w_y = u_y + v_s; h = u_x - A^T w_y
         struct V2 { T a, b; };
-        ew<V2>(m, [&](V2& r, int64_t i) { r.a = uy[i]; r.b = vs[i]; },
-               [&](V2& r, int64_t i) { wy[i] = (T)((double)r.a + (double)r.b); });
+        ew<V2>(m, [&](V2& r, int i) { r.a = uy[i]; r.b = vs[i]; },
+               [&](V2& r, int i) { wy[i] = (T)((double)r.a + (double)r.b); });
         __syncthreads();
         f_apply<T>(tb, d, 1, hx, wy, ux, -1.0, fa.kc, fsmem);
         // CG on (I + A^T A) z = h from the warm start (carried K z, A z)
         double s2[2] = {0.0, 0.0};   // ||r||^2, ||h||^2
-        ew<V2>(n, [&](V2& r, int64_t i) { r.a = hx[i]; r.b = kz[i]; },
-               [&](V2& r, int64_t i) {
+        ew<V2>(n, [&](V2& r, int i) { r.a = hx[i]; r.b = kz[i]; },
+               [&](V2& r, int i) {
                    const double hi = (double)r.a;
                    const T ri = (T)(hi - (double)r.b);
                    rx[i] = ri;
@@ -298,15 +301,15 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
             f_apply<T>(tb, d, 0, ty, px, nullptr, 1.0, fa.kc, fsmem);   // A p
             f_apply<T>(tb, d, 1, qx, ty, px, 1.0, fa.kc, fsmem);        // q = p + A^T A p
             double pq = 0.0;
-            ew<V2>(n, [&](V2& r, int64_t i) { r.a = px[i]; r.b = qx[i]; },
-                   [&](V2& r, int64_t i) { pq = fma((double)r.a, (double)r.b, pq); });
+            ew<V2>(n, [&](V2& r, int i) { r.a = px[i]; r.b = qx[i]; },
+                   [&](V2& r, int i) { pq = fma((double)r.a, (double)r.b, pq); });
             pq = bsum(pq, sh);
             const double a = rr / pq;
             if (!(pq > 0.0 && std::isfinite(a))) break;
             double rn = 0.0;
             struct V5 { T q, p, z, r, k; };
-            ew<V5>(n, [&](V5& r, int64_t i) { r.q = qx[i]; r.p = px[i]; r.z = zx[i]; r.r = rx[i]; r.k = kz[i]; },
-                   [&](V5& r, int64_t i) {
+            ew<V5>(n, [&](V5& r, int i) { r.q = qx[i]; r.p = px[i]; r.z = zx[i]; r.r = rx[i]; r.k = kz[i]; },
+                   [&](V5& r, int i) {
                        const double qi = (double)r.q;
                        zx[i] = (T)fma(a, (double)r.p, (double)r.z);
                        const T ri = (T)fma(-a, qi, (double)r.r);
@@ -314,8 +317,8 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
                        kz[i] = (T)fma(a, qi, (double)r.k);
                        rn = fma((double)ri, (double)ri, rn);
                    });
-            ew<V2>(m, [&](V2& r, int64_t i) { r.a = ty[i]; r.b = az[i]; },
-                   [&](V2& r, int64_t i) { az[i] = (T)fma(a, (double)r.a, (double)r.b); });
+            ew<V2>(m, [&](V2& r, int i) { r.a = ty[i]; r.b = az[i]; },
+                   [&](V2& r, int i) { az[i] = (T)fma(a, (double)r.a, (double)r.b); });
             rn = bsum(rn, sh);
             const double be = rr > 0.0 ? rn / rr : 0.0;
             rr = rn;
@@ -323,18 +326,18 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
             cgtot += 1.0;
             act = std::isfinite(rr) && sqrt(rr) > tol && cgit < fa.cg_max;
             if (act)
-                ew<V2>(n, [&](V2& r, int64_t i) { r.a = px[i]; r.b = rx[i]; },
-                       [&](V2& r, int64_t i) { px[i] = (T)fma(be, (double)r.a, (double)r.b); });
+                ew<V2>(n, [&](V2& r, int i) { r.a = px[i]; r.b = rx[i]; },
+                       [&](V2& r, int i) { px[i] = (T)fma(be, (double)r.a, (double)r.b); });
             __syncthreads();
         }
         if (cgit > cgmax) cgmax = cgit;
         // z_y = w_y + A z; u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta
         double s3[2] = {0.0, 0.0};   // c^T z_x, b^T z_y
-        ew<V2>(n, [&](V2& r, int64_t i) { r.a = cx[i]; r.b = zx[i]; },
-               [&](V2& r, int64_t i) { s3[0] = fma((double)r.a, (double)r.b, s3[0]); });
+        ew<V2>(n, [&](V2& r, int i) { r.a = cx[i]; r.b = zx[i]; },
+               [&](V2& r, int i) { s3[0] = fma((double)r.a, (double)r.b, s3[0]); });
         struct V3 { T w, a, b; };
-        ew<V3>(m, [&](V3& r, int64_t i) { r.w = wy[i]; r.a = az[i]; r.b = by[i]; },
-               [&](V3& r, int64_t i) {
+        ew<V3>(m, [&](V3& r, int i) { r.w = wy[i]; r.a = az[i]; r.b = by[i]; },
+               [&](V3& r, int i) {
                    const T zv = (T)((double)r.w + (double)r.a);
                    zy[i] = zv;
                    s3[1] = fma((double)r.b, (double)zv, s3[1]);
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         iter += 1.0;
         // relaxed point minus v_s of Y entry i, from its u_y, z_y, g_y, v_s
         struct V4 { T u, z, g, v; };
-        auto ld4y = [&](V4& r, int64_t i) { r.u = uy[i]; r.z = zy[i]; r.g = gy[i]; r.v = vs[i]; };
+        auto ld4y = [&](V4& r, int i) { r.u = uy[i]; r.z = zy[i]; r.g = gy[i]; r.v = vs[i]; };
         auto pv_of = [&](const V4& r) {
             const double ut_y = (double)r.z - ut * (double)r.g;
             const double ub = al * ut_y + (1.0 - al) * (double)r.u;
@@ -359,8 +362,8 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         for (int sgi = d.sg0; sgi < d.sg1; ++sgi) {
             const SocSeg sg = tb.seg[sgi];
             double ss = 0.0;
-            ew<V4>(sg.len - 1, [&](V4& r, int64_t i) { ld4y(r, sg.start + 1 + i); },
-                   [&](V4& r, int64_t) {
+            ew<V4>(sg.len - 1, [&](V4& r, int i) { ld4y(r, sg.start + 1 + i); },
+                   [&](V4& r, int) {
                        const double pv = pv_of(r);
                        ss = fma(pv, pv, ss);
                    });
@@ -375,11 +378,11 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         __syncthreads();
         // relaxation, projection, dual update
         struct V3x { T z, g, u; };
-        ew<V3x>(n, [&](V3x& r, int64_t i) { r.z = zx[i]; r.g = gx[i]; r.u = ux[i]; },
-                [&](V3x& r, int64_t i) {
+        ew<V3x>(n, [&](V3x& r, int i) { r.z = zx[i]; r.g = gx[i]; r.u = ux[i]; },
+                [&](V3x& r, int i) {
                     ux[i] = (T)(al * ((double)r.z - ut * (double)r.g) + (1.0 - al) * (double)r.u);
                 });
-        ew<V4>(d.l, ld4y, [&](V4& r, int64_t i) {
+        ew<V4>(d.l, ld4y, [&](V4& r, int i) {
             const double pv = pv_of(r);
             const double pr = pv > 0.0 ? pv : 0.0;
             uy[i] = (T)pr;
@@ -397,8 +400,8 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
                 mode = 2;
                 aa = 0.5 * (t + nz);
             }
-            ew<V4>(sg.len, [&](V4& r, int64_t i) { ld4y(r, sg.start + i); },
-                   [&](V4& r, int64_t i) {
+            ew<V4>(sg.len, [&](V4& r, int i) { ld4y(r, sg.start + i); },
+                   [&](V4& r, int i) {
                        const double pv = pv_of(r);
                        double pr;
                        if (mode == 0) pr = pv;
@@ -420,8 +423,8 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
         const T* ec = fv.x[XE];
         double r6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // Y: 0-2, X: 3-5
         struct V5y { T d, t, v, b, u; };
-        ew<V5y>(m, [&](V5y& r, int64_t i) { r.d = dr[i]; r.t = ty[i]; r.v = vs[i]; r.b = by[i]; r.u = uy[i]; },
-                [&](V5y& r, int64_t) {
+        ew<V5y>(m, [&](V5y& r, int i) { r.d = dr[i]; r.t = ty[i]; r.v = vs[i]; r.b = by[i]; r.u = uy[i]; },
+                [&](V5y& r, int) {
                     const double w = 1.0 / (double)r.d;
                     const double e = ((double)r.t + (double)r.v) * w;
                     const double rp = e - tau * (double)r.b * w;
@@ -430,8 +433,8 @@ __global__ __launch_bounds__(FNT) void k_fused(Tables tb, FusedArgs fa) {
                     r6[2] = fma((double)r.b, (double)r.u, r6[2]);
                 });
         struct V4x { T e, a, c, u; };
-        ew<V4x>(n, [&](V4x& r, int64_t i) { r.e = ec[i]; r.a = aty[i]; r.c = cx[i]; r.u = ux[i]; },
-                [&](V4x& r, int64_t) {
+        ew<V4x>(n, [&](V4x& r, int i) { r.e = ec[i]; r.a = aty[i]; r.c = cx[i]; r.u = ux[i]; },
+                [&](V4x& r, int) {
                     const double w = 1.0 / (double)r.e;
                     const double e = (double)r.a * w;
                     const double rd = e + tau * (double)r.c * w;
