@@ -304,14 +304,17 @@ DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<c
         const int64_t i = ck.at(j);
         v4<T> av = ld4<T>(azp, i), apv, wv, bv, uv, vv, gv;
         if (upd) apv = ld4<T>(app, i);
-        if (tw) {
-            wv = ld4<T>(wyp, i);
-            bv = ld4<T>(bp, i);
-        }
+        if (tw) bv = ld4<T>(bp, i);
         if (cone) {
+            // w_y = u_y + v_s as the projection (or k_wy) formed it from
+            // these stored values: recomputed instead of loaded
             uv = ld4<T>(uyp, i);
             vv = ld4<T>(vsp, i);
             gv = ld4<T>(gyp, i);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) wv[e] = (T)((double)uv[e] + (double)vv[e]);
+        } else if (tw) {
+            wv = ld4<T>(wyp, i);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
