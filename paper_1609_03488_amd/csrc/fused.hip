@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 
@@ -498,7 +499,7 @@ int64_t fused_resident_bytes(int prec, int64_t n, int64_t m) {
 
 // Dynamic LDS per workgroup that the fused kernels may take on each device
 // (0: not yet queried; then what fits in the 64 KB that needs no attribute)
-static int g_fused_lds[64] = {0};
+static std::atomic<int> g_fused_lds[64];   // (zero-initialised: static storage)
 
 static int fused_static_lds() {
     int b = 0;
@@ -511,7 +512,7 @@ static int fused_static_lds() {
 int fused_prepare() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536 - 1024;
-    if (g_fused_lds[dev] == 0) {
+    if (g_fused_lds[dev].load() == 0) {
         const int fixed = fused_static_lds();   // the kernels' own __shared__ arrays
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
@@ -523,16 +524,16 @@ int fused_prepare() {
              hipFuncSetAttribute((const void*)k_fused<float>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) !=
                  hipSuccess))
             dyn = 65536 - fixed;
-        g_fused_lds[dev] = dyn;
+        g_fused_lds[dev].store(dyn);   // (two threads that get here store the same value)
     }
-    return g_fused_lds[dev];
+    return g_fused_lds[dev].load();
 }
 
 void launch_fused(int prec, const Tables& t, FusedArgs fa, hipStream_t st) {
     if (t.ninst <= 0) return;
     int dev = 0;
-    const int cap = (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64 && g_fused_lds[dev] > 0)
-                        ? g_fused_lds[dev] : 65536 - 1024;
+    const int known = (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) ? g_fused_lds[dev].load() : 0;
+    const int cap = known > 0 ? known : 65536 - 1024;
     fa.lds_conv = ((int64_t)fused_smem_bytes(prec, fa.kc) + 15) & ~int64_t(15);
     fa.lds_res = std::max<int64_t>(0, std::min<int64_t>(fa.res_want, (int64_t)cap - fa.lds_conv));
     const size_t lds = (size_t)(fa.lds_conv + fa.lds_res);
