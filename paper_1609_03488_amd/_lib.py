@@ -129,7 +129,7 @@ def lib() -> C.CDLL:
         import torch  # noqa: F401
         if not os.path.exists(library_path):
             raise ImportError(f"{library_path} is missing; build it with "
-                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+                              "`python -m paper_1609_03488_amd.build_lib`")
         L = C.CDLL(library_path)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
