@@ -499,6 +499,37 @@ def test_server_result_same_alone_and_in_mix():
         np.testing.assert_array_equal(xa, xm)
 
 
+def test_fused_result_same_with_vectors_in_lds_or_memory():
+    """The fused kernel keeps an instance's most used vectors in LDS while they
+    fit next to the convolution's staging area, whose size is set by the
+    longest kernel in the launch.  Alone, every such vector of the (2500, 101)
+    request fits (with 160 KB of LDS per workgroup); next to a 1365-tap
+    request the staging area grows and z_y stays in global memory.  Where the
+    values sit must not change them."""
+    _say("fused lds residency")
+    reqs = [w.deconv_instance(n, k, k / 7.0, 0.05, 1e-4, 4100 + n) for n, k in ((2500, 101), (3000, 1365))]
+    prs = [P.deconv_problem(d["c"], d["b"]) for d in reqs]
+    st = P.Settings.make(precision=P.FP32, eps=1e-4, check_every=10, fused_max=16384)
+    alone = []
+    for pr in prs:
+        sv = P.Server(64 << 20, 8, st)
+        t = sv.submit(pr.op, pr.l, pr.q, pr.b, pr.c)
+        while sv.step(50):
+            pass
+        alone.append(sv.fetch(t))
+        sv.close()
+    sv = P.Server(64 << 20, 8, st)
+    tickets = [sv.submit(pr.op, pr.l, pr.q, pr.b, pr.c) for pr in prs]
+    while sv.step(50):
+        pass
+    mixed = [sv.fetch(t) for t in tickets]
+    sv.close()
+    for (xa, _, _, ia), (xm, _, _, im) in zip(alone, mixed):
+        assert ia["status"] == P.SOLVED and im["status"] == P.SOLVED
+        assert ia["iters"] == im["iters"]
+        np.testing.assert_array_equal(xa, xm)
+
+
 def test_server_results_match_oracle():
     """Served results against the oracle: a seeded Poisson trace with the
     serving workload's recipe (Section V-C deconvolution; log-uniform n, odd
