@@ -40,7 +40,8 @@ enum YVec : int {
     YG,       // g_y
     YB,       // b
     YW,       // w_y = u_y + v_s
-    YZ,       // z_y = w_y + A z_x
+    YZ,       // z_y = w_y + A z_x (stored by the fused kernel only; the other
+              // kernels form it from u_y, v_s and A z where they need it)
     YT,       // scratch (A p, A u_x)
     YA,       // A z, carried through the CG updates
     YD,       // row scaling D of the equilibrated operator D A E

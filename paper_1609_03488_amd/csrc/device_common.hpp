@@ -534,11 +534,20 @@ DEVI void init_tile(const Tables& tb, const InstDesc& d, const VecTile& tl, int 
     init_tile<T>(tb, d, tl, adj, out, in, base, sigma, 0, 0, 0, 0, f);
 }
 
+// z_y = w_y + A z in working precision, with w_y = u_y + v_s formed as the
+// projection stores it (the same two roundings as the update that ends CG,
+// which forms z_y for the tau products and does not store it)
+template <typename T>
+DEVI T z_y(T u, T v, T az) {
+    return (T)((double)(T)((double)u + (double)v) + (double)az);
+}
+
 // relaxed point minus v for a Y entry
 template <typename T>
 DEVI double ybar_minus_v(const InstDesc& d, int64_t i, double ut, double alpha, double& ubar) {
-    const double uy = (double)yvec<T>(d, YU)[i];
-    const double ut_y = (double)yvec<T>(d, YZ)[i] - ut * (double)yvec<T>(d, YG)[i];
+    const T u = yvec<T>(d, YU)[i];
+    const double uy = (double)u;
+    const double ut_y = (double)z_y<T>(u, yvec<T>(d, YV)[i], yvec<T>(d, YA)[i]) - ut * (double)yvec<T>(d, YG)[i];
     ubar = alpha * ut_y + (1.0 - alpha) * uy;
     return ubar - (double)yvec<T>(d, YV)[i];
 }

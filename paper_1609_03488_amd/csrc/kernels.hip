@@ -284,7 +284,6 @@ DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<c
     gptr<const T> app = yvec<T>(d, YT);
     gptr<const T> wyp = yvec<T>(d, YW);
     gptr<const T> bp = yvec<T>(d, YB);
-    gptr<T> zyp = yvec<T>(d, YZ);
     gptr<const T> uyp = yvec<T>(d, YU);
     gptr<const T> vsp = yvec<T>(d, YV);
     gptr<const T> gyp = yvec<T>(d, YG);
@@ -340,7 +339,7 @@ DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<c
             }
         }
         if (upd) st4<T>(azp, ck, j, av);
-        if (tw) st4<T>(zyp, ck, j, wv);
+        // (z_y is not stored: the projection forms it again from u_y, v_s and A z)
     }
     if (!tw) return;
     const int64_t ntl = (int64_t)tb.nx_tiles + tb.ny_tiles, b = (int64_t)tb.nx_tiles + xt.index;
@@ -462,22 +461,22 @@ __global__ __launch_bounds__(VEC_NT) void k_tau_dots(Tables tb, double alpha) {
     cg_elems<T>(tb, d, xt, sc, cs, false, 0.0, 0.0, false, false, true, XZ, XR, XP, XQ, sh);
 }
 
-// A thread's elements of a Y tile of u_y, z_y, g_y, v_s, loaded at once
+// A thread's elements of a Y tile of u_y, A z, g_y, v_s, loaded at once
 // (ahead of a reduction, and ahead of stores into the same vectors, which
 // element by element would order each load after the previous stores);
 // pv() is ybar_minus_v on them.
 template <typename T>
 struct YbarTile {
     static constexpr int R = VEC_TILE / VEC_NT;
-    T u[R], z[R], g[R], v[R];
+    T u[R], a[R], g[R], v[R];
     DEVI void load(const InstDesc& d, const VecTile& tl) {
-        gptr<const T> pu = yvec<T>(d, YU), pz = yvec<T>(d, YZ), pg = yvec<T>(d, YG), pvv = yvec<T>(d, YV);
+        gptr<const T> pu = yvec<T>(d, YU), pa = yvec<T>(d, YA), pg = yvec<T>(d, YG), pvv = yvec<T>(d, YV);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int64_t o = threadIdx.x + (int64_t)j * VEC_NT;
             const int64_t i = tl.start + (o < tl.len ? o : 0);
             u[j] = pu[i];
-            z[j] = pz[i];
+            a[j] = pa[i];
             g[j] = pg[i];
             v[j] = pvv[i];
         }
@@ -486,7 +485,7 @@ struct YbarTile {
     DEVI int64_t at(const VecTile& tl, int j) const { return tl.start + threadIdx.x + (int64_t)j * VEC_NT; }
     DEVI double pv(int j, double ut, double alpha) const {
         const double uy = (double)u[j];
-        const double ut_y = (double)z[j] - ut * (double)g[j];
+        const double ut_y = (double)z_y<T>(u[j], v[j], a[j]) - ut * (double)g[j];
         const double ub = alpha * ut_y + (1.0 - alpha) * uy;
         return ub - (double)v[j];
     }
