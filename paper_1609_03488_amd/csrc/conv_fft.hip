@@ -372,13 +372,13 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
     }
     // (a folded launch owns every X element)
     if (FOLD == 1) {
-        // h = value; r = h - K z, p = r written instead of h
+        // h = value; r = h - K z (and p = r when fp >= 0) written instead of h
         gptr<const float> kz = xvec<float>(d, cl.fq) + gw;
         float kv[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) kv[e] = kz[li[e] >= 0 ? li[e] : 0];
         gptr<float> rv = xvec<float>(d, cl.fr) + gw;
-        gptr<float> pv = xvec<float>(d, cl.fp) + gw;
+        gptr<float> pv = xvec<float>(d, cl.fp >= 0 ? cl.fp : cl.fr) + gw;   // (fp < 0: p is not written)
         float rrv[NE];
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
             const float rr = (float)(hd - (double)kv[e]);
             rrv[e] = rr;
             rv[li[e]] = rr;
-            pv[li[e]] = rr;
+            if (cl.fp >= 0) pv[li[e]] = rr;
             f.a += (double)rr * (double)rr;
             f.b += hd * hd;
         }

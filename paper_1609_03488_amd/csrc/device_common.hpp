@@ -396,7 +396,7 @@ struct Fold4 {
 
 // The CG work folded into an A^T launch for X element g whose apply output is
 // v (the arithmetic of k_cg_init and k_cg_dot):
-//   mode 1: h = v; r = h - x_fq, p = r are written (not h); a += r^2, b += h^2
+//   mode 1: h = v; r = h - x_fq (and p = r when fp >= 0) written (not h); a += r^2, b += h^2
 //   mode 2: q = v is written to `out`; a += p q, b += r^2, c += r q, d += q^2
 template <typename T>
 DEVI void fold_elem(const Tables& tb, const InstDesc& d, int mode, int fr, int fp, int fq, int out,
@@ -406,7 +406,7 @@ DEVI void fold_elem(const Tables& tb, const InstDesc& d, int mode, int fr, int f
         const double hd = (double)h;
         const T r = (T)(hd - (double)xvec<T>(d, fq)[g]);
         xvec<T>(d, fr)[g] = r;
-        xvec<T>(d, fp)[g] = r;
+        if (fp >= 0) xvec<T>(d, fp)[g] = r;
         f.a += (double)r * (double)r;
         f.b += hd * hd;
         if (idrows) {

@@ -806,24 +806,28 @@ void Engine::cg_iter(int z, int gate, int cg_max, int track, int it, int last, i
         // whatever the CG start test says (a step without CG iterations is
         // rare) and the update evaluates the test from the right-hand side's
         // partials, so no launch separates the right-hand side from A p
+        // p = r: this iteration reads the direction from r's vector (the
+        // right-hand side launch wrote r only) and its update writes the next
+        // direction to XP
         if (idrows) {
-            // (the identity rows of A p came with p from the right-hand side launch)
+            // (the identity rows of A p came with r from the right-hand side launch)
             for (ConvLaunch a : cf) {
                 a.ninit = 0;
-                conv(a, 0, YT, XP, -1, 1.0, G_ADMM);
+                conv(a, 0, YT, XR, -1, 1.0, G_ADMM);
             }
         } else {
-            apply(0, YT, XP, -1, 1.0, G_ADMM);
+            apply(0, YT, XR, -1, 1.0, G_ADMM);
         }
         ConvLaunch c = ca[0];
         c.fold = 2;
         c.fr = XR;
-        c.fp = XP;
+        c.fp = XR;
         c.fit = it;
         c.part = T.cpart;
-        conv(c, 1, XQ, YT, XP, 1.0, G_ADMM);
-        launch_cg_update(prec, T, z, XR, XP, XQ, it, cg_max, gate, track, stream, 1, last,
-                         CgStart{st.cg_tol, st.cg_rate, cg_floor(), 1, 1, 1, st.alpha});
+        conv(c, 1, XQ, YT, XR, 1.0, G_ADMM);
+        CgStart cs{st.cg_tol, st.cg_rate, cg_floor(), 1, 1, 1, st.alpha};
+        cs.pn = XP;
+        launch_cg_update(prec, T, z, XR, XR, XQ, it, cg_max, gate, track, stream, 1, last, cs);
         return;
     }
     apply(0, YT, XP, -1, 1.0, gate);
@@ -856,12 +860,12 @@ void Engine::admm_step() {
     // w_y = u_y + v_s was written by the previous step's projection (or refresh)
     if (folded_cg()) {
         // h = u_x - A^T w_y formed in the launch's epilogue, which writes
-        // r = h - K z and p = r (not h) and the CG start partials; the first
-        // CG update takes the start test
+        // r = h - K z (not h) and the CG start partials; the first CG
+        // update takes the start test
         ConvLaunch c = ca[0];
         c.fold = 1;
         c.fr = XR;
-        c.fp = XP;
+        c.fp = -1;   // (the first iteration reads p = r from XR)
         c.fq = XK;
         c.part = T.spart;
         c.idrows = idrows ? YT + 1 : 0;

@@ -222,7 +222,8 @@ DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<c
     if (!xt.is_y) {
         gptr<T> zp = xvec<T>(d, z);
         gptr<T> rp = xvec<T>(d, r);
-        gptr<T> pp = xvec<T>(d, p);
+        gptr<const T> pp = xvec<T>(d, p);
+        gptr<T> pw = xvec<T>(d, cs.pn >= 0 ? cs.pn : p);
         gptr<const T> qp = xvec<T>(d, q);
         gptr<T> kp = xvec<T>(d, XK);
         gptr<const T> cp = xvec<T>(d, XC);
@@ -258,7 +259,7 @@ DEVI void cg_elems(const Tables& tb, const InstDesc& d, const XYTile& xt, gptr<c
                 st4<T>(zp, ck, j, zv);
                 if (more) {
                     st4<T>(rp, ck, j, rv);
-                    st4<T>(pp, ck, j, pv);
+                    st4<T>(pw, ck, j, pv);
                 }
                 if (track) st4<T>(kp, ck, j, kv);
             }

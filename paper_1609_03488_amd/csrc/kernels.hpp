@@ -28,8 +28,8 @@ struct ConvLaunch {
     // CG steps folded into an A^T launch of the FFT engine that writes every X
     // element of every instance (fold != 0; partials in part[4 b + j] of
     // workgroup b):
-    //   1 (CG start): the output is h; r = h - q and p = r are written instead
-    //     of h (kinds fr, fp, fq), partials ||r||^2, ||h||^2;
+    //   1 (CG start): the output is h; r = h - q (and p = r when fp >= 0) is
+    //     written instead of h (kinds fr, fp, fq), partials ||r||^2, ||h||^2;
     //   2 (CG products): the output is q = p + A^T A p; partials <p, q>,
     //     ||r||^2, <r, q>, ||q||^2 (kinds fr, fp), and the iteration mark
     //     fit in the instance's scalars (the role of k_cg_dot)
@@ -108,6 +108,10 @@ struct CgStart {
     // partial slots 1 and 2
     int cone;
     double alpha;
+    // where the next direction p' = r' + beta p is written (-1: over p).  The
+    // first CG iteration of a folded ADMM step reads p = r from r's vector
+    // (the right-hand side launch does not copy it) and writes p' to XP.
+    int pn = -1;
 };
 void launch_cg_update(int prec, const Tables& t, int z, int r, int p, int q, int it, int cg_max,
                       int gate, int track, hipStream_t st, int folded = 0, int last = 0,
@@ -123,9 +127,9 @@ void launch_snapshot(int prec, const Tables& t, int restore, hipStream_t st);
 // ---- ADMM step pieces (Section V-B: subspace projection, then cone projection)
 // w_y = u_y + v_s
 void launch_wy(int prec, const Tables& t, int gate, hipStream_t st);
-// after CG on the one-launch-per-kernel path: z_y = w_y + (carried A z), the
-// partials of c^T z_x and b^T z_y and the cone terms of CgStart::cone (the
-// work the update that ends CG does on the folded path)
+// after CG on the one-launch-per-kernel path: the partials of c^T z_x and
+// b^T z_y, z_y = w_y + (carried A z) formed and not stored, and the cone terms
+// of CgStart::cone (the work the update that ends CG does on the folded path)
 void launch_tau_dots(int prec, const Tables& t, double alpha, hipStream_t st);
 // relaxation, projection onto K, dual update of every X/Y entry: every
 // workgroup forms u~_tau = (tau + kappa + c^T z_x + b^T z_y) / eta from the tau
