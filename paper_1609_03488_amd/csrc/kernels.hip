@@ -201,8 +201,8 @@ __global__ __launch_bounds__(VEC_NT) void k_cg_dot(Tables tb, int p, int q, int 
 }
 
 // The scalar products of u~_tau for one tile (Section V-B: the tau component
-// of the subspace projection): c^T z_x over an X tile, or z_y = w_y + A z
-// (the carried product) stored and b^T z_y over a Y tile; FP64 partial in
+// of the subspace projection): c^T z_x over an X tile, or b^T z_y over a Y
+// tile with z_y = w_y + A z (the carried product) formed, not stored; FP64 partial in
 // slot 0 of the tile's X or Y partials.  With CgStart::cone the cone terms of
 // the projection that follows are formed as well (see CgStart).
 //
@@ -447,8 +447,8 @@ __global__ __launch_bounds__(VEC_NT) void k_wy(Tables tb, int gate) {
 }
 
 // The products of u~_tau = (w_tau + c^T z_x + b^T z_y) / eta (exact solve of
-// (I+Q) u~ = w, last row) after CG, on the one-launch-per-kernel path: z_y =
-// w_y + (carried A z), the partials of c^T z_x and b^T z_y, and the cone terms
+// (I+Q) u~ = w, last row) after CG, on the one-launch-per-kernel path: the
+// partials of c^T z_x and b^T z_y (z_y = w_y + carried A z), and the cone terms
 // of the projection (the work the update that ends CG does on the folded path,
 // with z and A z as CG left them; CgStart::cone)
 template <typename T>
