@@ -326,16 +326,16 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
     const int64_t gw = g0 + oa;   // output vector position of offset 0
     // base + identity blocks of the owned range
     double bv[NE];
+    float bl[NE];   // the base values as loaded (FOLD 2: the base is p)
     {
         // (loads are unconditional, at the pair's first output where the
         // thread has no output, so that none sits behind a branch)
         if (base >= 0) {
             gptr<const float> bp = (adj ? xvec<float>(d, base) : yvec<float>(d, base)) + gw;
-            float l[NE];
 #pragma unroll
-            for (int e = 0; e < NE; ++e) l[e] = bp[li[e] >= 0 ? li[e] : 0];
+            for (int e = 0; e < NE; ++e) bl[e] = bp[li[e] >= 0 ? li[e] : 0];
 #pragma unroll
-            for (int e = 0; e < NE; ++e) bv[e] = li[e] >= 0 ? (double)l[e] : 0.0;
+            for (int e = 0; e < NE; ++e) bv[e] = li[e] >= 0 ? (double)bl[e] : 0.0;
         } else {
 #pragma unroll
             for (int e = 0; e < NE; ++e) bv[e] = 0.0;
@@ -410,14 +410,21 @@ __global__ __launch_bounds__(FT) void k_conv_fft(Tables tb, ConvLaunch cl, int a
             }
         }
     } else {
-        // q = value; partials <p, q>, ||r||^2, <r, q>, ||q||^2
+        // q = value; partials <p, q>, ||r||^2, <r, q>, ||q||^2.  p is the
+        // launch's base (q = p + A^T A p), already loaded; r is p's vector in
+        // a step's first iteration (p = r)
+        const bool p_base = base == cl.fp, r_p = cl.fr == cl.fp;
         gptr<const float> pp = xvec<float>(d, cl.fp) + gw;
         gptr<const float> rp = xvec<float>(d, cl.fr) + gw;
         float pvv[NE], rvv[NE];
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
-            pvv[e] = pp[li[e] >= 0 ? li[e] : 0];
-            rvv[e] = rp[li[e] >= 0 ? li[e] : 0];
+        for (int e = 0; e < NE; ++e) pvv[e] = p_base ? bl[e] : pp[li[e] >= 0 ? li[e] : 0];
+        if (r_p) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) rvv[e] = pvv[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) rvv[e] = rp[li[e] >= 0 ? li[e] : 0];
         }
         gptr<float> qo = xvec<float>(d, out) + gw;
 #pragma unroll
