@@ -705,9 +705,10 @@ def main():
     ap.add_argument("--serve-count", type=int, default=None)
     ap.add_argument("--serve-ws", type=int, default=16, help="server workspace, GiB")
     ap.add_argument("--serve-cg", type=int, default=3, help="CG iterations per step, upper bound")
-    ap.add_argument("--serve-fused-max", type=int, default=16384,
+    ap.add_argument("--serve-fused-max", type=int, default=3072,
                     help="largest n + m served by the fused one-workgroup-per-request path "
-                         "(larger requests take one launch per kernel)")
+                         "(larger requests take one launch per kernel; with 60-120 requests "
+                         "in flight the shared launches spread them over more of the chip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
